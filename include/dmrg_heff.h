@@ -1,0 +1,226 @@
+/*
+ * dmrg_heff.h - C ABI of the MI355X (gfx950) two-site DMRG effective
+ * Hamiltonian library.
+ *
+ * Method: Menczer et al., "Parallel implementation of the Density Matrix
+ * Renormalization Group method achieving a quarter petaFLOPS performance on a
+ * single DGX-H100 GPU node" (arXiv:2407.07411).  The paper minimises the
+ * energy of a matrix product state (Eq. 1, Eq. 2) one update at a time; each
+ * update is a large hermitian eigenproblem solved with Lanczos or Davidson,
+ * about 80% of the run time and O(D^3) (Numerical procedure section), followed
+ * by a matrix factorisation (Introduction).  This library is that update: the
+ * effective Hamiltonian H_eff acting on a block-sparse two-site wavefunction,
+ * its diagonal, its adjoint, a Davidson solver and the truncating SVD.
+ *
+ * Conventions shared by every call
+ *  - Quantum numbers are U(1)xU(1): (N, 2Sz) pairs of int32.
+ *  - A basis is the sector list of one enlarged block (block + one site).
+ *  - The two-site wavefunction psi with total quantum numbers Q stores one
+ *    block Psi[q, Q-q] for every left sector q (in basis order) whose partner
+ *    Q-q exists in the right basis; each block is row-major
+ *    d_L(q) x d_R(Q-q); blocks are contiguous in left-sector order.
+ *  - H_eff = sum over terms xi of c_xi * (O^L_xi (x) O^R_xi) with the
+ *    fermionic sign s = (-1)^{N(q_in)} on the input left sector when the term
+ *    is odd (each side changes the particle number by an odd amount):
+ *      Y[q+dq, Q-q-dq] += c * s * O^L[q+dq, q] Psi[q, Q-q] O^R[Q-q-dq, Q-q]^T.
+ *    A term with hc = 1 also applies its hermitian conjugate: the transposed
+ *    blocks with coefficient (-1)^odd * c.
+ *  - Every double pointer below is a DEVICE pointer owned by the caller unless
+ *    stated otherwise; integer tables are HOST pointers read during the call.
+ *  - Calls return dmrg_status (0 = success, negative = error) and never throw;
+ *    dmrg_last_error() returns a thread-local message for the last failure.
+ *  - Device work is enqueued on the context's HIP stream and is asynchronous
+ *    unless a call says it synchronises.
+ */
+#ifndef DMRG_HEFF_H
+#define DMRG_HEFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DMRG_OK = 0,
+  DMRG_EINVAL = -1,   /* bad argument: null pointer, negative size, bad enum   */
+  DMRG_EQN = -2,      /* quantum-number / layout violation (selection rule,    */
+                      /* block outside its pool, odd parity on a one-sided op) */
+  DMRG_ENOMEM = -3,   /* device or host allocation failed                      */
+  DMRG_EHIP = -4,     /* a HIP runtime call or kernel launch failed            */
+  DMRG_ENOCONV = -5,  /* Davidson stopped before reaching the tolerance        */
+  DMRG_ENOTSUP = -6   /* combination not supported by this build               */
+} dmrg_status;
+
+/* Arithmetic of the sector GEMMs.  Everything else (Davidson
+ * orthogonalisation, Rayleigh quotient, residuals, SVD) is always FP64. */
+typedef enum {
+  DMRG_FP64 = 0,          /* FP64 MFMA (v_mfma_f64_16x16x4)                    */
+  DMRG_SPLIT_BF16X3 = 1   /* operands split into 3 BF16 slices, products of    */
+                          /* slice pairs i+j<=2 on BF16 MFMA with FP32          */
+                          /* accumulation per K chunk, FP64 combine             */
+} dmrg_prec;
+
+typedef struct dmrg_ctx_s* dmrg_ctx_t;      /* device + borrowed HIP stream      */
+typedef struct dmrg_basis_s* dmrg_basis_t;  /* sector table of one block          */
+typedef struct dmrg_heff_s* dmrg_heff_t;    /* plan of one H_eff (work lists ...) */
+typedef struct dmrg_dav_s* dmrg_dav_t;      /* state of one Davidson solve        */
+
+/* ---- context ------------------------------------------------------------ */
+/* device: HIP device ordinal.  hip_stream: a hipStream_t borrowed from the
+ * caller (NULL = the null stream); the library never destroys it. */
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx_t* out);
+dmrg_status dmrg_ctx_set_stream(dmrg_ctx_t ctx, void* hip_stream);
+void dmrg_ctx_destroy(dmrg_ctx_t ctx);
+const char* dmrg_last_error(void);
+/* Name of the library build (arch and compile flags), static storage. */
+const char* dmrg_build_info(void);
+
+/* ---- bases and wavefunction layout --------------------------------------- */
+/* qn: host int32[n_sec][2] of distinct (N, 2Sz); dim: host int64[n_sec] >= 1.
+ * Errors: DMRG_EINVAL (null, n_sec < 1, dim < 1), DMRG_EQN (duplicate qn). */
+dmrg_status dmrg_basis_create(dmrg_ctx_t ctx, int32_t n_sec, const int32_t* qn,
+                              const int64_t* dim, dmrg_basis_t* out);
+void dmrg_basis_destroy(dmrg_basis_t b);
+/* Block layout of psi for total Q (host int32[2]).  n_blocks: number of
+ * blocks; block_offset (nullable, host int64[n_left_sectors]): offset of
+ * block Psi[q, Q-q] for every left sector, -1 where q has no partner;
+ * total: number of doubles of psi. */
+dmrg_status dmrg_wfn_layout(dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                            int64_t* n_blocks, int64_t* block_offset, int64_t* total);
+
+/* ---- effective Hamiltonian ------------------------------------------------ */
+/* One operator pair.  Operator blocks live in two caller-owned device pools of
+ * doubles.  left_off[a] (host int64[n_left_sectors]) is the offset in
+ * left_pool of block O^L[q_a + dq, q_a], row-major d_L(q_a+dq) x d_L(q_a), or
+ * -1 when absent; right_off[c] (host int64[n_right_sectors]) the offset of
+ * O^R[r_c - dq, r_c], row-major d_R(r_c-dq) x d_R(r_c), or -1.
+ * one_sided = 1: O^L (x) 1 (right_off ignored, may be NULL, dq must be 0,
+ * odd must be 0); one_sided = 2: 1 (x) O^R (left_off ignored).  Blocks whose
+ * input or output wavefunction block does not exist are ignored. */
+typedef struct {
+  int32_t dq[2];     /* left shift (dN, d2Sz); the right side shifts by -dq  */
+  int32_t odd;       /* 1: fermion-odd pair, sign (-1)^{N(q_in)}            */
+  int32_t hc;        /* 1: also apply the hermitian-conjugate term          */
+  int32_t one_sided; /* 0 two-sided, 1 left only, 2 right only              */
+  int32_t reserved;  /* must be 0                                            */
+  double coeff;
+  const int64_t* left_off;
+  const int64_t* right_off;
+} dmrg_term;
+
+/* Builds the plan: wavefunction layout, the (term, block) work list with the
+ * cheaper association order per pair, the grouped-GEMM tile lists and the
+ * device workspace.  The pools are borrowed (must outlive the plan, contents
+ * may change between applies); pool lengths are in doubles and bound-check
+ * every block.  Errors: DMRG_EINVAL, DMRG_EQN (block out of its pool, dq that
+ * leaves the basis, odd one-sided term), DMRG_ENOMEM, DMRG_EHIP.
+ * Synchronises the context stream. */
+dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
+                             const int32_t Q[2], int64_t n_terms, const dmrg_term* terms,
+                             const double* left_pool, int64_t left_pool_len,
+                             const double* right_pool, int64_t right_pool_len,
+                             dmrg_prec prec, dmrg_heff_t* out);
+void dmrg_heff_destroy(dmrg_heff_t h);
+dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec);
+/* Host, synchronous.  alg_flops: FP64-equivalent FLOPs of one matvec, every
+ * (term, block) pair counted once per hc partner at its cheaper association
+ * order (one-sided pairs: one GEMM).  alg_bytes: every operator block used
+ * read once plus psi read plus y written, 8 bytes per double. */
+dmrg_status dmrg_heff_flops(dmrg_heff_t h, double* alg_flops, double* alg_bytes);
+/* Length of psi in doubles (== dmrg_wfn_layout total). */
+int64_t dmrg_heff_size(dmrg_heff_t h);
+/* y = H_eff psi.  psi and y: device double[size], must not overlap. */
+dmrg_status dmrg_heff_apply(dmrg_heff_t h, const double* psi, double* y);
+/* diag = diagonal of H_eff (device double[size]): only dq = 0 pairs reach
+ * the diagonal, each as c * diag(O^L) (x) diag(O^R). */
+dmrg_status dmrg_heff_diag(dmrg_heff_t h, double* diag);
+/* Adjoint of y = H_eff(O) psi for an upstream gradient ybar (device
+ * double[size]).  Each non-null output is ACCUMULATED (+=):
+ *   psibar         += H_eff^T ybar                      (device double[size])
+ *   left_pool_bar  += d<ybar, y>/d left_pool   (device, left_pool layout)
+ *   right_pool_bar += d<ybar, y>/d right_pool  (device, right_pool layout)
+ * Intermediates are recomputed, not stored from the forward pass. */
+dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const double* ybar,
+                                    double* psibar, double* left_pool_bar,
+                                    double* right_pool_bar);
+/* Bytes of device workspace the plan holds (T intermediates of the
+ * two-GEMM chains, processed in waves that fit it). */
+int64_t dmrg_heff_workspace_bytes(dmrg_heff_t h);
+/* Capture the matvec for the (psi, y) pair in a hipGraph and replay it on
+ * later applies with the same pointers (1) or launch eagerly (0). */
+dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable);
+
+/* Profiling: the matvec is a fixed sequence of grouped-GEMM launches.
+ * n_launches (host) receives their number; when kernel / flops are non-null
+ * (host arrays of at least that many entries) they receive each launch's
+ * kernel id (0: 32x32 tile, 1: 64x64, 2: 128x128; +16 for the split-precision
+ * kernels) and its algorithmic FLOPs (2 M N K summed over its problems). */
+dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops);
+/* y = H_eff psi as dmrg_heff_apply (eager), bracketing every launch with HIP
+ * events on the context stream; ms (host float[n_launches]) receives each
+ * launch's duration.  Synchronises the stream. */
+dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y, float* ms);
+
+/* ---- Davidson -------------------------------------------------------------- */
+typedef struct {
+  int32_t max_iter;      /* iterations (matvecs after the first), e.g. 200   */
+  int32_t max_subspace;  /* basis size before restart, 2..32, e.g. 24        */
+  int32_t restart_keep;  /* Ritz vectors kept at restart, 1..max_subspace-1  */
+  int32_t use_graph;     /* 1: replay each iteration as one hipGraph         */
+  double tol;            /* stop when ||H x - theta x||_2 <= tol, ||x|| = 1  */
+  int32_t fp64_tail;     /* split precision: iterations run in FP64 after the */
+                         /* split-precision phase stalls (0 = none)           */
+  int32_t reserved;
+} dmrg_dav_opts;
+typedef struct {
+  double energy;         /* Ritz value theta (Rayleigh quotient in FP64)     */
+  double residual;       /* ||H x - theta x||_2 of the returned vector       */
+  int32_t iters;
+  int32_t matvecs;
+  int32_t converged;
+  int32_t tail_iters;    /* iterations spent in the FP64 tail                 */
+} dmrg_dav_result;
+
+/* Davidson (E. R. Davidson 1975) for the lowest eigenpair of H_eff with the
+ * diagonal preconditioner t = r / (theta - diag) (|theta - diag| clamped to
+ * >= 1e-8), two-pass classical Gram-Schmidt, restart from the restart_keep
+ * lowest Ritz vectors.  psi0 (device double[size], non-zero) is the start
+ * vector.  Device memory: (2 * max_subspace + 8) * size doubles. */
+dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts,
+                                 const double* psi0, dmrg_dav_t* out);
+/* One iteration: Rayleigh-Ritz on the current subspace, residual, and (when
+ * not converged) correction, orthogonalisation and one matvec.  Synchronises
+ * the stream to read the residual.  Returns DMRG_OK while iterating or once
+ * converged (res->converged), DMRG_ENOCONV when max_iter is exhausted or the
+ * correction vanished. */
+dmrg_status dmrg_davidson_step(dmrg_dav_t d, dmrg_dav_result* res);
+/* Copy the current Ritz vector (unit norm) to x (device double[size]). */
+dmrg_status dmrg_davidson_vector(dmrg_dav_t d, double* x);
+void dmrg_davidson_destroy(dmrg_dav_t d);
+/* Whole solve: create, iterate, write the Ritz vector back into psi_inout. */
+dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts,
+                          dmrg_dav_result* res);
+
+/* ---- SVD truncation --------------------------------------------------------- */
+/* Factorises each block Psi[q, Q-q] = U S V^T (one-sided Jacobi, FP64),
+ * pools all singular values, sorts them descending (ties: lower left-sector
+ * index first, then position) and keeps at most max_keep values > cutoff.
+ * psi: device double[size] in the layout of (L, R, Q).
+ * kept_dim: host int64[n_left_sectors], number of values kept per left sector
+ *   (0 for sectors without a block).
+ * U, Vt, S: device outputs, each block's factors packed in left-sector order:
+ *   U block d_L(q) x k_q row-major, S k_q values (descending within the
+ *   block), Vt block k_q x d_R(Q-q) row-major; capacities u_cap, s_cap,
+ *   vt_cap in doubles (DMRG_EINVAL if too small; the needed sizes are what
+ *   the call would write with max_keep = total rank).
+ * trunc_err (host): sum of discarded sigma^2.  Synchronises. */
+dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                              const double* psi, int64_t max_keep, double cutoff,
+                              int64_t* kept_dim, double* U, int64_t u_cap, double* S,
+                              int64_t s_cap, double* Vt, int64_t vt_cap, double* trunc_err);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMRG_HEFF_H */

@@ -128,8 +128,11 @@ def _get(pools, spec, trans):
     return m.T if trans else m
 
 
-def heff_apply(prob, psi=None, terms=None, left_pool=None, right_pool=None):
-    """y = H_eff psi, plain definition, float64, left-first, ascending terms."""
+def heff_apply(prob, psi=None, terms=None, left_pool=None, right_pool=None, out_left_sectors=None):
+    """y = H_eff psi, plain definition, float64, left-first, ascending terms.
+
+    out_left_sectors (optional set of left-sector indices) restricts the
+    computation to those output blocks; the other blocks stay zero."""
     lay = layout_of(prob)
     pools = {"L": _np(prob.left_pool if left_pool is None else left_pool),
              "R": _np(prob.right_pool if right_pool is None else right_pool)}
@@ -137,6 +140,8 @@ def heff_apply(prob, psi=None, terms=None, left_pool=None, right_pool=None):
     y = np.zeros(lay.total)
     for t in (prob.terms if terms is None else terms):
         for (a, b, A, tA, B, tB, alpha) in term_items(lay, t):
+            if out_left_sectors is not None and b not in out_left_sectors:
+                continue
             X = lay.block(x, a)
             Yb = lay.block(y, b)
             if A is not None:

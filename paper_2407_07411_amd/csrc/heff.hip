@@ -1,0 +1,252 @@
+// Host side of the C ABI: contexts, bases, the wavefunction layout and the
+// H_eff plan (work lists for the grouped GEMM kernels).
+//
+// A plan turns the operator-pair terms into "items": one per (term, input
+// wavefunction block), plus one per hermitian-conjugate partner.  Each
+// two-sided item is a two-GEMM chain Y_out += alpha * op(A) X_in op(B)^T; the
+// planner picks the cheaper association (left-first T = op(A) X_in, or
+// right-first W = X_in op(B)^T), stores the intermediate in a device
+// workspace (phase 1), and sums all intermediates of one output block as one
+// long-K GEMM (phase 2).  Items are processed in waves so that the
+// intermediates of one wave fit the workspace.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <set>
+#include <string>
+
+#include "plan.h"
+
+namespace dmrg {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+dmrg_status fail(dmrg_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+dmrg_status Program::upload() {
+  release();
+  auto put = [](auto& vec, auto** dptr) -> dmrg_status {
+    using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+    size_t bytes = std::max<size_t>(1, vec.size()) * sizeof(T);
+    if (hipMalloc((void**)dptr, bytes) != hipSuccess) {
+      *dptr = nullptr;
+      return fail(DMRG_ENOMEM, "hipMalloc of plan tables failed");
+    }
+    if (!vec.empty())
+      DMRG_HIP(hipMemcpy(*dptr, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice));
+    return DMRG_OK;
+  };
+  dmrg_status st;
+  if ((st = put(probs, &d_probs)) != DMRG_OK) return st;
+  if ((st = put(segs, &d_segs)) != DMRG_OK) return st;
+  if ((st = put(tiles, &d_tiles)) != DMRG_OK) return st;
+  return DMRG_OK;
+}
+
+dmrg_status Program::validate(const int64_t* len) const {
+  auto in = [&](uint8_t buf, int64_t lo, int64_t hi) {  // [lo, hi] inclusive
+    return buf < BUF_COUNT && lo >= 0 && hi < len[buf];
+  };
+  for (size_t pi = 0; pi < probs.size(); ++pi) {
+    const Prob& p = probs[pi];
+    if (p.M < 1 || p.N < 1 || p.ldc < p.N || p.seg0 < 0 || p.nseg < 0 ||
+        (size_t)p.seg0 + p.nseg > segs.size())
+      return fail(DMRG_EQN, "plan: malformed problem " + std::to_string(pi));
+    if (!in(p.cbuf, p.coff, p.coff + (int64_t)(p.M - 1) * p.ldc + p.N - 1))
+      return fail(DMRG_EQN, "plan: output of problem " + std::to_string(pi) + " out of bounds");
+    for (int s = p.seg0; s < p.seg0 + p.nseg; ++s) {
+      const Seg& g = segs[s];
+      if (g.K < 1) return fail(DMRG_EQN, "plan: empty segment");
+      const int64_t xhi = g.xt ? g.xoff + (int64_t)(g.K - 1) * g.ldx + p.M - 1
+                               : g.xoff + (int64_t)(p.M - 1) * g.ldx + g.K - 1;
+      const int64_t zhi = g.zt ? g.zoff + (int64_t)(p.N - 1) * g.ldz + g.K - 1
+                               : g.zoff + (int64_t)(g.K - 1) * g.ldz + p.N - 1;
+      const bool xok = g.xt ? g.ldx >= p.M : g.ldx >= g.K;
+      const bool zok = g.zt ? g.ldz >= g.K : g.ldz >= p.N;
+      if (!xok || !zok || !in(g.xbuf, g.xoff, xhi) || !in(g.zbuf, g.zoff, zhi))
+        return fail(DMRG_EQN, "plan: operand of problem " + std::to_string(pi) + " out of bounds");
+    }
+  }
+  for (const Launch& l : launches) {
+    if (l.tile0 < 0 || l.ntiles < 0 || l.tile0 + l.ntiles > (int64_t)tiles.size())
+      return fail(DMRG_EQN, "plan: launch outside the tile table");
+    const int bm = cfg_bm(l.cfg), bn = cfg_bn(l.cfg);
+    for (int64_t i = l.tile0; i < l.tile0 + l.ntiles; ++i) {
+      const Tile& t = tiles[i];
+      if (t.prob < 0 || (size_t)t.prob >= probs.size() || t.tm < 0 || t.tn < 0 ||
+          (int64_t)t.tm * bm >= probs[t.prob].M || (int64_t)t.tn * bn >= probs[t.prob].N)
+        return fail(DMRG_EQN, "plan: tile outside its problem");
+    }
+  }
+  return DMRG_OK;
+}
+
+void Program::release() {
+  if (d_probs) (void)hipFree(d_probs);
+  if (d_segs) (void)hipFree(d_segs);
+  if (d_tiles) (void)hipFree(d_tiles);
+  d_probs = nullptr;
+  d_segs = nullptr;
+  d_tiles = nullptr;
+}
+
+dmrg_status Program::run(const Bases& b, hipStream_t s, int precision) const {
+  for (const Launch& l : launches) {
+    Launch x = l;
+    x.split = precision;
+    dmrg_status st = launch_gemm(x, b, d_probs, d_segs, d_tiles, s);
+    if (st != DMRG_OK) return st;
+  }
+  return DMRG_OK;
+}
+
+// Tile shape for one output matrix.
+int choose_cfg(int M, int N) {
+  if (M >= 96 && N >= 96) return CFG_F64_128;
+  if (M >= 40 && N >= 40) return CFG_F64_64;
+  return CFG_F64_32;
+}
+
+// Appends the tiles of `probs[first..)` grouped by tile configuration, one
+// launch per configuration.
+void ProgramBuilder::close_phase() {
+  std::vector<std::vector<Tile>> per(CFG_F64_COUNT);
+  for (size_t pi = phase_first; pi < prog.probs.size(); ++pi) {
+    const Prob& p = prog.probs[pi];
+    int cfg = cfg_override >= 0 ? cfg_override : choose_cfg(p.M, p.N);
+    int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
+    int tm = (p.M + bm - 1) / bm, tn = (p.N + bn - 1) / bn;
+    for (int i = 0; i < tm; ++i)
+      for (int j = 0; j < tn; ++j) per[cfg].push_back(Tile{(int32_t)pi, (int16_t)i, (int16_t)j});
+  }
+  for (int c = CFG_F64_COUNT - 1; c >= 0; --c) {
+    if (per[c].empty()) continue;
+    Launch l{c, 0, (int64_t)prog.tiles.size(), (int64_t)per[c].size()};
+    prog.tiles.insert(prog.tiles.end(), per[c].begin(), per[c].end());
+    prog.launches.push_back(l);
+  }
+  phase_first = prog.probs.size();
+}
+
+int32_t ProgramBuilder::add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta) {
+  Prob p{};
+  p.coff = coff;
+  p.M = M;
+  p.N = N;
+  p.ldc = ldc;
+  p.seg0 = (int32_t)prog.segs.size();
+  p.nseg = 0;
+  p.cbuf = cbuf;
+  p.beta = beta ? 1 : 0;
+  prog.probs.push_back(p);
+  return (int32_t)prog.probs.size() - 1;
+}
+
+void ProgramBuilder::add_seg(int32_t prob, const Seg& s) {
+  // segments of one problem are contiguous: problems are filled one at a time
+  prog.segs.push_back(s);
+  prog.probs[prob].nseg++;
+}
+
+Seg make_seg(uint8_t xbuf, int64_t xoff, int ldx, bool xt, uint8_t zbuf, int64_t zoff, int ldz,
+             bool zt, int K, double alpha) {
+  Seg s{};
+  s.xoff = xoff;
+  s.zoff = zoff;
+  s.K = K;
+  s.ldx = ldx;
+  s.ldz = ldz;
+  s.xbuf = xbuf;
+  s.zbuf = zbuf;
+  s.xt = xt ? 1 : 0;
+  s.zt = zt ? 1 : 0;
+  s.alpha = alpha;
+  return s;
+}
+
+}  // namespace dmrg
+
+using namespace dmrg;
+
+int dmrg_basis_s::find(int32_t n, int32_t sz) const {
+  for (size_t i = 0; i < dim.size(); ++i)
+    if (qn[2 * i] == n && qn[2 * i + 1] == sz) return (int)i;
+  return -1;
+}
+
+extern "C" {
+
+const char* dmrg_last_error(void) { return g_last_error.c_str(); }
+
+const char* dmrg_build_info(void) {
+  return "dmrg_heff gfx950: FP64 MFMA 16x16x4 grouped GEMM, BF16x3 split MFMA 16x16x32";
+}
+
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx_t* out) {
+  if (!out) return fail(DMRG_EINVAL, "ctx_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  DMRG_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DMRG_EINVAL, "ctx_create: bad device ordinal");
+  DMRG_HIP(hipSetDevice(device));
+  auto* c = new (std::nothrow) dmrg_ctx_s{device, (hipStream_t)hip_stream};
+  if (!c) return fail(DMRG_ENOMEM, "ctx_create: out of host memory");
+  *out = c;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_ctx_set_stream(dmrg_ctx_t ctx, void* hip_stream) {
+  if (!ctx) return fail(DMRG_EINVAL, "ctx_set_stream: ctx is NULL");
+  ctx->stream = (hipStream_t)hip_stream;
+  return DMRG_OK;
+}
+
+void dmrg_ctx_destroy(dmrg_ctx_t ctx) { delete ctx; }
+
+dmrg_status dmrg_basis_create(dmrg_ctx_t ctx, int32_t n_sec, const int32_t* qn, const int64_t* dim,
+                              dmrg_basis_t* out) {
+  if (!out) return fail(DMRG_EINVAL, "basis_create: out is NULL");
+  *out = nullptr;
+  if (!ctx || !qn || !dim || n_sec < 1) return fail(DMRG_EINVAL, "basis_create: bad arguments");
+  std::set<std::pair<int32_t, int32_t>> seen;
+  for (int i = 0; i < n_sec; ++i) {
+    if (dim[i] < 1 || dim[i] > (int64_t)1 << 30)
+      return fail(DMRG_EINVAL, "basis_create: sector dimension out of range");
+    if (!seen.insert({qn[2 * i], qn[2 * i + 1]}).second)
+      return fail(DMRG_EQN, "basis_create: duplicate quantum numbers");
+  }
+  auto* b = new (std::nothrow) dmrg_basis_s;
+  if (!b) return fail(DMRG_ENOMEM, "basis_create: out of host memory");
+  b->ctx = ctx;
+  b->qn.assign(qn, qn + 2 * n_sec);
+  b->dim.assign(dim, dim + n_sec);
+  *out = b;
+  return DMRG_OK;
+}
+
+void dmrg_basis_destroy(dmrg_basis_t b) { delete b; }
+
+dmrg_status dmrg_wfn_layout(dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2], int64_t* n_blocks,
+                            int64_t* block_offset, int64_t* total) {
+  if (!L || !R || !Q) return fail(DMRG_EINVAL, "wfn_layout: bad arguments");
+  int64_t off = 0, nb = 0;
+  for (size_t a = 0; a < L->dim.size(); ++a) {
+    int c = R->find(Q[0] - L->qn[2 * a], Q[1] - L->qn[2 * a + 1]);
+    if (block_offset) block_offset[a] = c < 0 ? -1 : off;
+    if (c < 0) continue;
+    off += L->dim[a] * R->dim[c];
+    ++nb;
+  }
+  if (n_blocks) *n_blocks = nb;
+  if (total) *total = off;
+  return DMRG_OK;
+}
+
+}  // extern "C"

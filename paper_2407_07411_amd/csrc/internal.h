@@ -1,0 +1,138 @@
+// Internal declarations shared by the host planner and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmrg_heff.h"
+
+namespace dmrg {
+
+// ---------------------------------------------------------------------------
+// Error handling: a thread-local message plus a status code.
+void set_error(const std::string& msg);
+dmrg_status fail(dmrg_status st, const std::string& msg);
+#define DMRG_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::dmrg::fail(DMRG_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Grouped-GEMM work description.  Operands are named by a buffer id and an
+// offset so that a plan does not depend on the caller's psi / y pointers; the
+// base pointers are passed by value at launch.
+enum BufId : uint8_t {
+  BUF_PSI = 0,    // input vector of the matvec
+  BUF_Y = 1,      // output vector
+  BUF_LPOOL = 2,  // left operator pool
+  BUF_RPOOL = 3,  // right operator pool
+  BUF_WORK = 4,   // intermediates of the two-GEMM chains
+  BUF_YBAR = 5,   // upstream gradient (adjoint)
+  BUF_GL = 6,     // left pool gradient (adjoint)
+  BUF_GR = 7,     // right pool gradient (adjoint)
+  BUF_COUNT = 8
+};
+struct Bases {
+  double* p[BUF_COUNT];
+};
+
+// One K segment of an output tile:  C += alpha * X (M x K) * Z (K x N).
+//   xt = 0: X[m][k] = x[m*ldx + k]      xt = 1: X[m][k] = x[k*ldx + m]
+//   zt = 0: Z[k][n] = z[k*ldz + n]      zt = 1: Z[k][n] = z[n*ldz + k]
+struct Seg {
+  int64_t xoff, zoff;
+  int32_t K, ldx, ldz;
+  uint8_t xbuf, zbuf, xt, zt;
+  double alpha;
+};
+static_assert(sizeof(Seg) == 40, "Seg layout");
+
+// One output matrix C (M x N, row stride ldc) = [beta ? C : 0] + sum of its
+// segments in order.
+struct Prob {
+  int64_t coff;
+  int32_t M, N, ldc, seg0, nseg;
+  uint8_t cbuf, beta, pad0, pad1;
+};
+static_assert(sizeof(Prob) == 32, "Prob layout");
+
+// One output tile of one problem.
+struct Tile {
+  int32_t prob;
+  int16_t tm, tn;
+};
+static_assert(sizeof(Tile) == 8, "Tile layout");
+
+// Tile shapes the kernels are instantiated for.
+enum TileCfg : int32_t {
+  CFG_F64_32 = 0,   // 32x32 tile, 1 wave (2x2 MFMA blocks)
+  CFG_F64_64 = 1,   // 64x64 tile, 4 waves (2x2 each)
+  CFG_F64_128 = 2,  // 128x128 tile, 4 waves (4x4 each)
+  CFG_F64_COUNT = 3
+};
+int cfg_bm(int cfg);
+int cfg_bn(int cfg);
+
+// A launch of the grouped GEMM over a contiguous range of the tile table.
+struct Launch {
+  int32_t cfg;
+  int32_t split;     // 0 FP64, 1 split BF16x3
+  int64_t tile0;
+  int64_t ntiles;
+};
+
+// A program: ordered launches over one set of device tables.
+struct Program {
+  std::vector<Prob> probs;
+  std::vector<Seg> segs;
+  std::vector<Tile> tiles;
+  std::vector<Launch> launches;
+  Prob* d_probs = nullptr;
+  Seg* d_segs = nullptr;
+  Tile* d_tiles = nullptr;
+  dmrg_status upload();
+  void release();
+  // Host-side bounds proof of every access the kernels will make, given the
+  // length (in doubles) of each buffer id.  Run before the first launch.
+  dmrg_status validate(const int64_t* buf_len) const;
+  dmrg_status run(const Bases& b, hipStream_t s, int precision) const;
+};
+
+dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
+                        const Tile* tiles, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Diagonal: per wavefunction block, the dq = 0 pairs that reach it.
+struct DiagItem {
+  int64_t aoff, boff;   // stored block offsets (-1: identity on that side)
+  int32_t da, db;       // stored block sizes (square)
+  double alpha;
+};
+struct DiagBlock {
+  int64_t off;
+  int32_t dl, dr, item0, nitem;
+};
+dmrg_status launch_diag(const DiagBlock* blocks, int nblocks, const DiagItem* items,
+                        const double* lpool, const double* rpool, double* out, int64_t max_elems,
+                        hipStream_t s);
+
+}  // namespace dmrg
+
+// ---------------------------------------------------------------------------
+// Opaque handle definitions.
+struct dmrg_ctx_s {
+  int device;
+  hipStream_t stream;
+};
+
+struct dmrg_basis_s {
+  dmrg_ctx_t ctx;
+  std::vector<int32_t> qn;   // [n][2]
+  std::vector<int64_t> dim;  // [n]
+  int find(int32_t n, int32_t sz) const;
+};

@@ -1,0 +1,84 @@
+// Plan structures of one effective Hamiltonian.
+#pragma once
+
+#include <map>
+#include <vector>
+
+#include "internal.h"
+
+namespace dmrg {
+
+// One wavefunction block Psi[q_a, Q - q_a].
+struct BlockInfo {
+  int32_t a, c;      // left / right sector
+  int32_t dl, dr;    // rows, columns
+  int64_t off;       // offset in psi
+};
+
+// One contribution Y[out] += alpha * op(A) X[in] op(B)^T.  A and B name the
+// STORED blocks (rows x cols as stored); at / bt say that the stored block
+// enters transposed.  kind: 0 two-sided, 1 left only, 2 right only.
+struct Item {
+  int32_t in, out;
+  int64_t aoff;
+  int32_t arows, acols;
+  int64_t boff;
+  int32_t brows, bcols;
+  uint8_t at, bt, kind, pad;
+  int32_t term;
+  double alpha;
+};
+
+struct ProgramBuilder {
+  Program prog;
+  size_t phase_first = 0;
+  int cfg_override = -1;
+  int32_t add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta);
+  void add_seg(int32_t prob, const Seg& s);
+  void close_phase();
+};
+
+dmrg_status heff_apply_eager(struct ::dmrg_heff_s* h, const double* psi, double* y);
+Seg make_seg(uint8_t xbuf, int64_t xoff, int ldx, bool xt, uint8_t zbuf, int64_t zoff, int ldz,
+             bool zt, int K, double alpha);
+int choose_cfg(int M, int N);
+
+}  // namespace dmrg
+
+struct dmrg_heff_s {
+  dmrg_ctx_t ctx = nullptr;
+  std::vector<int32_t> Lqn, Rqn;
+  std::vector<int64_t> Ld, Rd;
+  int32_t Q[2] = {0, 0};
+  std::vector<dmrg::BlockInfo> blocks;
+  std::vector<int32_t> blk_of_left;  // left sector -> block or -1
+  int64_t size = 0;
+  std::vector<dmrg::Item> items;
+  const double* lpool = nullptr;
+  const double* rpool = nullptr;
+  int64_t llen = 0, rlen = 0;
+  double flops = 0.0, bytes = 0.0;
+  int prec = DMRG_FP64;
+  int64_t work_budget = 0;  // doubles
+  double* work = nullptr;
+  int64_t work_elems = 0;
+  dmrg::Program fwd;
+  dmrg::Program adj;
+  bool adj_built = false;
+  int adj_mask = 0;
+  bool adj_psibar = false, adj_left = false, adj_right = false;
+  double* adj_work = nullptr;
+  int64_t adj_work_elems = 0;
+  // diagonal
+  dmrg::DiagBlock* d_dblocks = nullptr;
+  dmrg::DiagItem* d_ditems = nullptr;
+  int n_dblocks = 0;
+  int64_t max_block_elems = 0;
+  // graph cache for the matvec
+  int use_graph = 0;
+  const double* g_psi = nullptr;
+  double* g_y = nullptr;
+  int g_prec = -1;
+  hipGraphExec_t g_exec = nullptr;
+  hipGraph_t g_graph = nullptr;
+};

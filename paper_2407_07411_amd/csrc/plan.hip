@@ -1,0 +1,738 @@
+// H_eff plan: validation of the operator-pair terms, the item list, the
+// forward and adjoint grouped-GEMM programs, the diagonal tables, and the
+// C entry points that run them.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <memory>
+#include <new>
+#include <set>
+#include <string>
+
+#include "plan.h"
+
+using namespace dmrg;
+
+namespace {
+
+int64_t env_workspace_doubles() {
+  const char* s = std::getenv("DMRG_HEFF_WORKSPACE_MB");
+  int64_t mb = s ? std::atoll(s) : 2048;
+  if (mb < 1) mb = 1;
+  return mb * (1 << 20) / 8;
+}
+
+int cfg_from_env() {
+  const char* s = std::getenv("DMRG_HEFF_TILE");
+  if (!s) return -1;
+  int v = std::atoi(s);
+  if (v == 32) return CFG_F64_32;
+  if (v == 64) return CFG_F64_64;
+  if (v == 128) return CFG_F64_128;
+  return -1;
+}
+
+// Cost of the two association orders of one two-sided item (FLOPs).
+void item_costs(const dmrg_heff_s* h, const Item& it, double* lf, double* rf) {
+  const BlockInfo& bi = h->blocks[it.in];
+  const BlockInfo& bo = h->blocks[it.out];
+  const double dli = bi.dl, dri = bi.dr, dlo = bo.dl, dro = bo.dr;
+  *lf = 2.0 * dlo * dli * dri + 2.0 * dlo * dri * dro;
+  *rf = 2.0 * dli * dri * dro + 2.0 * dlo * dli * dro;
+}
+
+dmrg_status build_items(dmrg_heff_s* h, int64_t n_terms, const dmrg_term* terms) {
+  const int nL = (int)h->Ld.size(), nR = (int)h->Rd.size();
+  auto findL = [&](int32_t n, int32_t s) {
+    for (int i = 0; i < nL; ++i)
+      if (h->Lqn[2 * i] == n && h->Lqn[2 * i + 1] == s) return i;
+    return -1;
+  };
+  auto findR = [&](int32_t n, int32_t s) {
+    for (int i = 0; i < nR; ++i)
+      if (h->Rqn[2 * i] == n && h->Rqn[2 * i + 1] == s) return i;
+    return -1;
+  };
+  for (int64_t ti = 0; ti < n_terms; ++ti) {
+    const dmrg_term& t = terms[ti];
+    const std::string where = "term " + std::to_string(ti) + ": ";
+    if (t.one_sided < 0 || t.one_sided > 2 || t.reserved != 0 || (t.odd != 0 && t.odd != 1) ||
+        (t.hc != 0 && t.hc != 1) || !std::isfinite(t.coeff))
+      return fail(DMRG_EINVAL, where + "bad flags or coefficient");
+    if (t.one_sided && (t.dq[0] != 0 || t.dq[1] != 0 || t.odd))
+      return fail(DMRG_EQN, where + "a one-sided term must have dq = 0 and even parity");
+    if (t.odd != (std::abs(t.dq[0]) % 2))
+      return fail(DMRG_EQN, where + "parity flag does not match the particle-number shift");
+    const bool hasL = t.one_sided != 2, hasR = t.one_sided != 1;
+    if ((hasL && !t.left_off) || (hasR && !t.right_off))
+      return fail(DMRG_EINVAL, where + "missing offset table");
+    // selection rules and pool bounds of every stored block
+    std::vector<int> outL(nL, -1), outR(nR, -1);
+    if (hasL)
+      for (int a = 0; a < nL; ++a) {
+        if (t.left_off[a] < 0) continue;
+        int b = findL(h->Lqn[2 * a] + t.dq[0], h->Lqn[2 * a + 1] + t.dq[1]);
+        if (b < 0) return fail(DMRG_EQN, where + "left block maps to a sector outside the basis");
+        if (t.left_off[a] + h->Ld[b] * h->Ld[a] > h->llen)
+          return fail(DMRG_EQN, where + "left block outside the left pool");
+        outL[a] = b;
+      }
+    if (hasR)
+      for (int c = 0; c < nR; ++c) {
+        if (t.right_off[c] < 0) continue;
+        int e = findR(h->Rqn[2 * c] - t.dq[0], h->Rqn[2 * c + 1] - t.dq[1]);
+        if (e < 0) return fail(DMRG_EQN, where + "right block maps to a sector outside the basis");
+        if (t.right_off[c] + h->Rd[e] * h->Rd[c] > h->rlen)
+          return fail(DMRG_EQN, where + "right block outside the right pool");
+        outR[c] = e;
+      }
+    for (size_t bi = 0; bi < h->blocks.size(); ++bi) {
+      const BlockInfo& B = h->blocks[bi];
+      Item it{};
+      it.term = (int32_t)ti;
+      if (t.one_sided == 1) {
+        if (t.left_off[B.a] < 0) continue;
+        it.in = it.out = (int32_t)bi;
+        it.aoff = t.left_off[B.a];
+        it.arows = it.acols = B.dl;
+        it.boff = -1;
+        it.kind = 1;
+        it.alpha = t.coeff;
+        h->items.push_back(it);
+        if (t.hc) {
+          it.at = 1;
+          h->items.push_back(it);
+        }
+        continue;
+      }
+      if (t.one_sided == 2) {
+        if (t.right_off[B.c] < 0) continue;
+        it.in = it.out = (int32_t)bi;
+        it.aoff = -1;
+        it.boff = t.right_off[B.c];
+        it.brows = it.bcols = B.dr;
+        it.kind = 2;
+        it.alpha = t.coeff;
+        h->items.push_back(it);
+        if (t.hc) {
+          it.bt = 1;
+          h->items.push_back(it);
+        }
+        continue;
+      }
+      const int b = outL[B.a];
+      if (b < 0 || t.right_off[B.c] < 0) continue;
+      const int ob = h->blk_of_left[b];
+      if (ob < 0) continue;  // output block outside the wavefunction
+      const BlockInfo& O = h->blocks[ob];
+      if (outR[B.c] != O.c) return fail(DMRG_EQN, where + "left and right shifts do not match");
+      const double s_in = (t.odd && (h->Lqn[2 * B.a] & 1)) ? -1.0 : 1.0;
+      it.in = (int32_t)bi;
+      it.out = ob;
+      it.aoff = t.left_off[B.a];
+      it.arows = O.dl;
+      it.acols = B.dl;
+      it.boff = t.right_off[B.c];
+      it.brows = O.dr;
+      it.bcols = B.dr;
+      it.kind = 0;
+      it.alpha = t.coeff * s_in;
+      h->items.push_back(it);
+      if (t.hc) {
+        Item p = it;
+        p.in = ob;
+        p.out = (int32_t)bi;
+        p.at = p.bt = 1;
+        const double s_p = (t.odd && (h->Lqn[2 * O.a] & 1)) ? -1.0 : 1.0;
+        p.alpha = (t.odd ? -t.coeff : t.coeff) * s_p;
+        h->items.push_back(p);
+      }
+    }
+  }
+  return DMRG_OK;
+}
+
+void count_work(dmrg_heff_s* h) {
+  double fl = 0.0;
+  std::set<int64_t> lused, rused;
+  double ob = 0.0;
+  for (const Item& it : h->items) {
+    const BlockInfo& bi = h->blocks[it.in];
+    const BlockInfo& bo = h->blocks[it.out];
+    if (it.kind == 1) {
+      fl += 2.0 * bo.dl * bi.dl * bi.dr;
+    } else if (it.kind == 2) {
+      fl += 2.0 * bi.dl * bi.dr * bo.dr;
+    } else {
+      double lf, rf;
+      item_costs(h, it, &lf, &rf);
+      fl += std::min(lf, rf);
+    }
+    if (it.aoff >= 0 && lused.insert(it.aoff).second) ob += (double)it.arows * it.acols;
+    if (it.boff >= 0 && rused.insert(it.boff).second) ob += (double)it.brows * it.bcols;
+  }
+  h->flops = fl;
+  h->bytes = 8.0 * (ob + 2.0 * (double)h->size);
+}
+
+// op(A) of an item as the X operand of a segment (M = rows of op(A)).
+void opA_as_x(const Item& it, bool* xt, int* ldx) {
+  *xt = it.at != 0;  // stored rows x cols; transposed use reads column-wise
+  *ldx = it.acols;
+}
+
+// op(B)^T as the Z operand (K = columns of op(B)).
+void opBt_as_z(const Item& it, bool* zt, int* ldz) {
+  *zt = it.bt == 0;
+  *ldz = it.bcols;
+}
+
+// Forward program: phase 1 computes T = alpha op(A) X (left-first) or
+// W = alpha X op(B)^T (right-first) for the wave's two-sided items; phase 2
+// writes each output block once per wave as a long-K sum.
+dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
+  ProgramBuilder pb;
+  pb.cfg_override = cfg_override;
+  const int nb = (int)h->blocks.size();
+  std::vector<std::vector<int32_t>> by_out(nb);
+  for (size_t i = 0; i < h->items.size(); ++i) by_out[h->items[i].out].push_back((int32_t)i);
+  std::vector<uint8_t> written(nb, 0);
+  std::vector<double> lf_first(h->items.size());
+  int64_t max_need = 0;
+  for (size_t i = 0; i < h->items.size(); ++i) {
+    const Item& it = h->items[i];
+    if (it.kind != 0) continue;
+    double lf, rf;
+    item_costs(h, it, &lf, &rf);
+    lf_first[i] = lf <= rf ? 1.0 : 0.0;
+    const BlockInfo& bi = h->blocks[it.in];
+    const BlockInfo& bo = h->blocks[it.out];
+    int64_t need = lf_first[i] ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
+    max_need = std::max(max_need, need);
+  }
+  const int64_t budget = std::max(h->work_budget, max_need);
+  // waves over output blocks (items of one block stay together when possible)
+  struct Wave {
+    std::vector<std::pair<int32_t, int64_t>> items;  // item, workspace offset
+  };
+  std::vector<Wave> waves(1);
+  int64_t used = 0, peak = 0;
+  for (int ob = 0; ob < nb; ++ob) {
+    for (int32_t ii : by_out[ob]) {
+      const Item& it = h->items[ii];
+      int64_t need = 0;
+      if (it.kind == 0) {
+        const BlockInfo& bi = h->blocks[it.in];
+        const BlockInfo& bo = h->blocks[it.out];
+        need = lf_first[ii] ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
+      }
+      if (used + need > budget && !waves.back().items.empty()) {
+        waves.emplace_back();
+        used = 0;
+      }
+      waves.back().items.push_back({ii, used});
+      used += need;
+      peak = std::max(peak, used);
+    }
+  }
+  h->work_elems = std::max<int64_t>(peak, 1);
+  for (size_t w = 0; w < waves.size(); ++w) {
+    // phase 1
+    for (auto& pr : waves[w].items) {
+      const Item& it = h->items[pr.first];
+      if (it.kind != 0) continue;
+      const BlockInfo& bi = h->blocks[it.in];
+      const BlockInfo& bo = h->blocks[it.out];
+      bool xt, zt;
+      int ldx, ldz;
+      if (lf_first[pr.first]) {
+        int32_t p = pb.add_prob(BUF_WORK, pr.second, bo.dl, bi.dr, bi.dr, false);
+        opA_as_x(it, &xt, &ldx);
+        pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
+                               it.alpha));
+      } else {
+        int32_t p = pb.add_prob(BUF_WORK, pr.second, bi.dl, bo.dr, bo.dr, false);
+        opBt_as_z(it, &zt, &ldz);
+        pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt, bi.dr,
+                               it.alpha));
+      }
+    }
+    pb.close_phase();
+    // phase 2: one problem per output block present in the wave
+    std::map<int32_t, std::vector<std::pair<int32_t, int64_t>>> per_out;
+    for (auto& pr : waves[w].items) per_out[h->items[pr.first].out].push_back(pr);
+    if (w == 0)
+      for (int ob = 0; ob < nb; ++ob)
+        if (by_out[ob].empty()) per_out[ob];  // blocks nothing reaches are written as zeros
+    for (auto& kv : per_out) {
+      const BlockInfo& bo = h->blocks[kv.first];
+      int32_t p = pb.add_prob(BUF_Y, bo.off, bo.dl, bo.dr, bo.dr, written[kv.first] != 0);
+      written[kv.first] = 1;
+      for (auto& pr : kv.second) {
+        const Item& it = h->items[pr.first];
+        const BlockInfo& bi = h->blocks[it.in];
+        bool xt, zt;
+        int ldx, ldz;
+        if (it.kind == 1) {
+          opA_as_x(it, &xt, &ldx);
+          pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
+                                 it.alpha));
+        } else if (it.kind == 2) {
+          opBt_as_z(it, &zt, &ldz);
+          pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt, bi.dr,
+                                 it.alpha));
+        } else if (lf_first[pr.first]) {
+          opBt_as_z(it, &zt, &ldz);
+          pb.add_seg(p, make_seg(BUF_WORK, pr.second, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt,
+                                 bi.dr, 1.0));
+        } else {
+          opA_as_x(it, &xt, &ldx);
+          pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_WORK, pr.second, bo.dr, false,
+                                 bi.dl, 1.0));
+        }
+      }
+    }
+    pb.close_phase();
+  }
+  h->fwd = std::move(pb.prog);
+  return DMRG_OK;
+}
+
+// Adjoint program.  Phase 1, per two-sided item: U = alpha ybar_out op(B)
+// and V = alpha op(A) X_in (both d_L(out) x d_R(in)).  Phase 2 accumulates
+//   psibar_in            += op(A)^T U
+//   stored A (direct)    += U X_in^T        stored A (transposed use) += X_in U^T
+//   stored B (direct)    += ybar_out^T V    stored B (transposed use) += V^T ybar_out
+// and the one-sided analogues directly from ybar.
+dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
+  ProgramBuilder pb;
+  pb.cfg_override = cfg_override;
+  const int64_t nitems = (int64_t)h->items.size();
+  std::vector<int64_t> woff(nitems, -1);
+  int64_t budget = std::max<int64_t>(h->work_budget, 1);
+  for (const Item& it : h->items)
+    if (it.kind == 0)
+      budget = std::max<int64_t>(budget, 2 * (int64_t)h->blocks[it.out].dl * h->blocks[it.in].dr);
+  int64_t i0 = 0;
+  int64_t peak = 0;
+  while (i0 < nitems) {
+    int64_t used = 0, i1 = i0;
+    while (i1 < nitems) {
+      const Item& it = h->items[i1];
+      int64_t need = it.kind == 0 ? 2 * (int64_t)h->blocks[it.out].dl * h->blocks[it.in].dr : 0;
+      if (used + need > budget && i1 > i0) break;
+      woff[i1] = used;
+      used += need;
+      ++i1;
+    }
+    peak = std::max(peak, used);
+    // phase 1
+    for (int64_t i = i0; i < i1; ++i) {
+      const Item& it = h->items[i];
+      if (it.kind != 0) continue;
+      const BlockInfo& bi = h->blocks[it.in];
+      const BlockInfo& bo = h->blocks[it.out];
+      const int64_t u = woff[i], v = woff[i] + (int64_t)bo.dl * bi.dr;
+      // U = alpha ybar_out (dlo x dro) op(B) (dro x dri): op(B) as Z directly
+      {
+        int32_t p = pb.add_prob(BUF_WORK, u, bo.dl, bi.dr, bi.dr, false);
+        // Z[k][n] = op(B)[k][n]: stored direct -> row-major; transposed -> zt
+        pb.add_seg(p, make_seg(BUF_YBAR, bo.off, bo.dr, false, BUF_RPOOL, it.boff, it.bcols,
+                               it.bt != 0, bo.dr, it.alpha));
+      }
+      // V = alpha op(A) X_in
+      {
+        int32_t p = pb.add_prob(BUF_WORK, v, bo.dl, bi.dr, bi.dr, false);
+        bool xt;
+        int ldx;
+        opA_as_x(it, &xt, &ldx);
+        pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
+                               it.alpha));
+      }
+    }
+    pb.close_phase();
+    // phase 2: psibar blocks, left-pool blocks, right-pool blocks
+    std::map<int32_t, std::vector<int64_t>> by_in;
+    std::map<int64_t, std::vector<int64_t>> by_a, by_b;
+    for (int64_t i = i0; i < i1; ++i) {
+      const Item& it = h->items[i];
+      by_in[it.in].push_back(i);
+      if (it.aoff >= 0) by_a[it.aoff].push_back(i);
+      if (it.boff >= 0) by_b[it.boff].push_back(i);
+    }
+    if (h->adj_psibar) {
+      for (auto& kv : by_in) {
+        const BlockInfo& bi = h->blocks[kv.first];
+        int32_t p = pb.add_prob(BUF_Y, bi.off, bi.dl, bi.dr, bi.dr, true);
+        for (int64_t i : kv.second) {
+          const Item& it = h->items[i];
+          const BlockInfo& bo = h->blocks[it.out];
+          // op(A)^T as X: stored direct -> transposed read; transposed use -> direct
+          if (it.kind == 0) {
+            pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, it.acols, it.at == 0, BUF_WORK, woff[i],
+                                   bi.dr, false, bo.dl, 1.0));
+          } else if (it.kind == 1) {
+            pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, it.acols, it.at == 0, BUF_YBAR, bo.off,
+                                   bo.dr, false, bo.dl, it.alpha));
+          } else {
+            // psibar += alpha ybar op(B): Z[k][n] = op(B)[k][n]
+            pb.add_seg(p, make_seg(BUF_YBAR, bo.off, bo.dr, false, BUF_RPOOL, it.boff, it.bcols,
+                                   it.bt != 0, bo.dr, it.alpha));
+          }
+        }
+      }
+    }
+    if (h->adj_left) {
+      for (auto& kv : by_a) {
+        const Item& f = h->items[kv.second[0]];
+        int32_t p = pb.add_prob(BUF_GL, kv.first, f.arows, f.acols, f.acols, true);
+        for (int64_t i : kv.second) {
+          const Item& it = h->items[i];
+          const BlockInfo& bi = h->blocks[it.in];
+          const BlockInfo& bo = h->blocks[it.out];
+          if (it.kind == 0) {
+            if (!it.at)  // U (dlo x dri) X_in^T
+              pb.add_seg(p, make_seg(BUF_WORK, woff[i], bi.dr, false, BUF_PSI, bi.off, bi.dr, true,
+                                     bi.dr, 1.0));
+            else  // X_in (dli x dri) U^T
+              pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_WORK, woff[i], bi.dr, true,
+                                     bi.dr, 1.0));
+          } else {  // one-sided left: alpha ybar X_in^T, or alpha X_in ybar^T
+            if (!it.at)
+              pb.add_seg(p, make_seg(BUF_YBAR, bo.off, bo.dr, false, BUF_PSI, bi.off, bi.dr, true,
+                                     bi.dr, it.alpha));
+            else
+              pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_YBAR, bo.off, bo.dr, true,
+                                     bi.dr, it.alpha));
+          }
+        }
+      }
+    }
+    if (h->adj_right) {
+      for (auto& kv : by_b) {
+        const Item& f = h->items[kv.second[0]];
+        int32_t p = pb.add_prob(BUF_GR, kv.first, f.brows, f.bcols, f.bcols, true);
+        for (int64_t i : kv.second) {
+          const Item& it = h->items[i];
+          const BlockInfo& bi = h->blocks[it.in];
+          const BlockInfo& bo = h->blocks[it.out];
+          if (it.kind == 0) {
+            const int64_t v = woff[i] + (int64_t)bo.dl * bi.dr;
+            if (!it.bt)  // ybar_out^T (dro x dlo) V (dlo x dri)
+              pb.add_seg(p, make_seg(BUF_YBAR, bo.off, bo.dr, true, BUF_WORK, v, bi.dr, false,
+                                     bo.dl, 1.0));
+            else  // V^T (dri x dlo) ybar_out (dlo x dro)
+              pb.add_seg(p, make_seg(BUF_WORK, v, bi.dr, true, BUF_YBAR, bo.off, bo.dr, false,
+                                     bo.dl, 1.0));
+          } else {  // one-sided right: alpha ybar^T X_in, or alpha X_in^T ybar
+            if (!it.bt)
+              pb.add_seg(p, make_seg(BUF_YBAR, bo.off, bo.dr, true, BUF_PSI, bi.off, bi.dr, false,
+                                     bo.dl, it.alpha));
+            else
+              pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, true, BUF_YBAR, bo.off, bo.dr, false,
+                                     bo.dl, it.alpha));
+          }
+        }
+      }
+    }
+    pb.close_phase();
+    i0 = i1;
+  }
+  h->adj_work_elems = std::max<int64_t>(peak, 1);
+  h->adj = std::move(pb.prog);
+  return DMRG_OK;
+}
+
+dmrg_status build_diag(dmrg_heff_s* h) {
+  std::vector<DiagBlock> db;
+  std::vector<DiagItem> di;
+  const int nb = (int)h->blocks.size();
+  std::vector<std::vector<int32_t>> by_out(nb);
+  for (size_t i = 0; i < h->items.size(); ++i)
+    if (h->items[i].in == h->items[i].out) by_out[h->items[i].out].push_back((int32_t)i);
+  h->max_block_elems = 0;
+  for (int b = 0; b < nb; ++b) {
+    const BlockInfo& B = h->blocks[b];
+    DiagBlock d{B.off, B.dl, B.dr, (int32_t)di.size(), 0};
+    for (int32_t i : by_out[b]) {
+      const Item& it = h->items[i];
+      // in == out means dq = 0 for two-sided items: square stored blocks
+      di.push_back(DiagItem{it.aoff, it.boff, it.acols, it.bcols, it.alpha});
+      d.nitem++;
+    }
+    db.push_back(d);
+    h->max_block_elems = std::max<int64_t>(h->max_block_elems, (int64_t)B.dl * B.dr);
+  }
+  h->n_dblocks = nb;
+  if (hipMalloc(&h->d_dblocks, std::max<size_t>(1, db.size()) * sizeof(DiagBlock)) != hipSuccess ||
+      hipMalloc(&h->d_ditems, std::max<size_t>(1, di.size()) * sizeof(DiagItem)) != hipSuccess)
+    return fail(DMRG_ENOMEM, "hipMalloc of diagonal tables failed");
+  if (!db.empty())
+    DMRG_HIP(hipMemcpy(h->d_dblocks, db.data(), db.size() * sizeof(DiagBlock), hipMemcpyHostToDevice));
+  if (!di.empty())
+    DMRG_HIP(hipMemcpy(h->d_ditems, di.data(), di.size() * sizeof(DiagItem), hipMemcpyHostToDevice));
+  return DMRG_OK;
+}
+
+void free_graph(dmrg_heff_s* h) {
+  if (h->g_exec) (void)hipGraphExecDestroy(h->g_exec);
+  if (h->g_graph) (void)hipGraphDestroy(h->g_graph);
+  h->g_exec = nullptr;
+  h->g_graph = nullptr;
+  h->g_psi = nullptr;
+  h->g_y = nullptr;
+}
+
+Bases fwd_bases(dmrg_heff_s* h, const double* psi, double* y) {
+  Bases b{};
+  b.p[BUF_PSI] = const_cast<double*>(psi);
+  b.p[BUF_Y] = y;
+  b.p[BUF_LPOOL] = const_cast<double*>(h->lpool);
+  b.p[BUF_RPOOL] = const_cast<double*>(h->rpool);
+  b.p[BUF_WORK] = h->work;
+  return b;
+}
+
+}  // namespace
+
+namespace dmrg {
+dmrg_status heff_apply_eager(dmrg_heff_s* h, const double* psi, double* y) {
+  return h->fwd.run(fwd_bases(h, psi, y), h->ctx->stream, h->prec);
+}
+}  // namespace dmrg
+
+extern "C" {
+
+dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                             int64_t n_terms, const dmrg_term* terms, const double* left_pool,
+                             int64_t left_pool_len, const double* right_pool,
+                             int64_t right_pool_len, dmrg_prec prec, dmrg_heff_t* out) {
+  if (!out) return fail(DMRG_EINVAL, "heff_create: out is NULL");
+  *out = nullptr;
+  if (!ctx || !L || !R || !Q || n_terms < 0 || (n_terms > 0 && !terms))
+    return fail(DMRG_EINVAL, "heff_create: bad arguments");
+  if (left_pool_len < 0 || right_pool_len < 0 || (left_pool_len > 0 && !left_pool) ||
+      (right_pool_len > 0 && !right_pool))
+    return fail(DMRG_EINVAL, "heff_create: bad pool");
+  if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3)
+    return fail(DMRG_EINVAL, "heff_create: unknown precision");
+  std::unique_ptr<dmrg_heff_s> h(new (std::nothrow) dmrg_heff_s);
+  if (!h) return fail(DMRG_ENOMEM, "heff_create: out of host memory");
+  h->ctx = ctx;
+  h->Lqn = L->qn;
+  h->Rqn = R->qn;
+  h->Ld = L->dim;
+  h->Rd = R->dim;
+  h->Q[0] = Q[0];
+  h->Q[1] = Q[1];
+  h->lpool = left_pool;
+  h->rpool = right_pool;
+  h->llen = left_pool_len;
+  h->rlen = right_pool_len;
+  h->prec = prec;
+  h->blk_of_left.assign(L->dim.size(), -1);
+  int64_t off = 0;
+  for (size_t a = 0; a < L->dim.size(); ++a) {
+    int c = R->find(Q[0] - L->qn[2 * a], Q[1] - L->qn[2 * a + 1]);
+    if (c < 0) continue;
+    h->blk_of_left[a] = (int32_t)h->blocks.size();
+    h->blocks.push_back(BlockInfo{(int32_t)a, c, (int32_t)L->dim[a], (int32_t)R->dim[c], off});
+    off += L->dim[a] * R->dim[c];
+  }
+  h->size = off;
+  if (h->blocks.empty()) return fail(DMRG_EQN, "heff_create: no wavefunction block has total Q");
+  if (h->blocks.size() > 65535) return fail(DMRG_ENOTSUP, "heff_create: too many blocks");
+  for (const BlockInfo& b : h->blocks)
+    if (b.dl > 32767 * 32 || b.dr > 32767 * 32)
+      return fail(DMRG_ENOTSUP, "heff_create: sector too large");
+  dmrg_status st = build_items(h.get(), n_terms, terms);
+  if (st != DMRG_OK) return st;
+  count_work(h.get());
+  h->work_budget = env_workspace_doubles();
+  if ((st = build_forward(h.get(), cfg_from_env())) != DMRG_OK) return st;
+  {
+    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0};
+    if ((st = h->fwd.validate(len)) != DMRG_OK) return st;
+  }
+  if ((st = h->fwd.upload()) != DMRG_OK) return st;
+  if (hipMalloc(&h->work, h->work_elems * sizeof(double)) != hipSuccess) {
+    h->work = nullptr;
+    h->fwd.release();
+    return fail(DMRG_ENOMEM, "heff_create: workspace allocation failed");
+  }
+  if ((st = build_diag(h.get())) != DMRG_OK) {
+    h->fwd.release();
+    (void)hipFree(h->work);
+    return st;
+  }
+  *out = h.release();
+  return DMRG_OK;
+}
+
+void dmrg_heff_destroy(dmrg_heff_t h) {
+  if (!h) return;
+  free_graph(h);
+  h->fwd.release();
+  h->adj.release();
+  if (h->work) (void)hipFree(h->work);
+  if (h->adj_work) (void)hipFree(h->adj_work);
+  if (h->d_dblocks) (void)hipFree(h->d_dblocks);
+  if (h->d_ditems) (void)hipFree(h->d_ditems);
+  delete h;
+}
+
+dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec) {
+  if (!h) return fail(DMRG_EINVAL, "set_precision: h is NULL");
+  if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3)
+    return fail(DMRG_EINVAL, "set_precision: unknown precision");
+  h->prec = prec;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_flops(dmrg_heff_t h, double* alg_flops, double* alg_bytes) {
+  if (!h) return fail(DMRG_EINVAL, "heff_flops: h is NULL");
+  if (alg_flops) *alg_flops = h->flops;
+  if (alg_bytes) *alg_bytes = h->bytes;
+  return DMRG_OK;
+}
+
+int64_t dmrg_heff_size(dmrg_heff_t h) { return h ? h->size : -1; }
+
+int64_t dmrg_heff_workspace_bytes(dmrg_heff_t h) {
+  return h ? 8 * (h->work_elems + (h->adj_work ? h->adj_work_elems : 0)) : -1;
+}
+
+dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable) {
+  if (!h) return fail(DMRG_EINVAL, "use_graph: h is NULL");
+  h->use_graph = enable ? 1 : 0;
+  if (!enable) free_graph(h);
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_apply(dmrg_heff_t h, const double* psi, double* y) {
+  if (!h || !psi || !y) return fail(DMRG_EINVAL, "heff_apply: bad arguments");
+  if (psi == y) return fail(DMRG_EINVAL, "heff_apply: psi and y must not alias");
+  hipStream_t s = h->ctx->stream;
+  if (!h->use_graph) return heff_apply_eager(h, psi, y);
+  if (!h->g_exec || h->g_psi != psi || h->g_y != y || h->g_prec != h->prec) {
+    free_graph(h);
+    if (s == nullptr) return fail(DMRG_EINVAL, "heff_apply: graph capture needs a non-null stream");
+    DMRG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    dmrg_status st = heff_apply_eager(h, psi, y);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != DMRG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(DMRG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    h->g_graph = g;
+    DMRG_HIP(hipGraphInstantiate(&h->g_exec, g, nullptr, nullptr, 0));
+    h->g_psi = psi;
+    h->g_y = y;
+    h->g_prec = h->prec;
+  }
+  DMRG_HIP(hipGraphLaunch(h->g_exec, s));
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops) {
+  if (!h || !n_launches) return fail(DMRG_EINVAL, "heff_launches: bad arguments");
+  const auto& P = h->fwd;
+  *n_launches = (int64_t)P.launches.size();
+  for (size_t i = 0; i < P.launches.size(); ++i) {
+    const Launch& l = P.launches[i];
+    if (kernel) kernel[i] = l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : 0);
+    if (flops) {
+      double f = 0.0;
+      int64_t last = -1;
+      for (int64_t t = l.tile0; t < l.tile0 + l.ntiles; ++t) {
+        const int32_t pi = P.tiles[t].prob;
+        if (pi == last) continue;  // tiles of one problem are contiguous
+        last = pi;
+        const Prob& p = P.probs[pi];
+        for (int sg = p.seg0; sg < p.seg0 + p.nseg; ++sg) f += 2.0 * p.M * p.N * P.segs[sg].K;
+      }
+      flops[i] = f;
+    }
+  }
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y, float* ms) {
+  if (!h || !psi || !y || !ms) return fail(DMRG_EINVAL, "heff_apply_profiled: bad arguments");
+  hipStream_t s = h->ctx->stream;
+  const auto& P = h->fwd;
+  const size_t n = P.launches.size();
+  std::vector<hipEvent_t> ev(n + 1, nullptr);
+  dmrg_status st = DMRG_OK;
+  for (size_t i = 0; i <= n && st == DMRG_OK; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) st = fail(DMRG_EHIP, "hipEventCreate failed");
+  const Bases b = fwd_bases(h, psi, y);
+  if (st == DMRG_OK && hipEventRecord(ev[0], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
+  for (size_t i = 0; i < n && st == DMRG_OK; ++i) {
+    Launch x = P.launches[i];
+    x.split = h->prec;
+    st = launch_gemm(x, b, P.d_probs, P.d_segs, P.d_tiles, s);
+    if (st == DMRG_OK && hipEventRecord(ev[i + 1], s) != hipSuccess)
+      st = fail(DMRG_EHIP, "hipEventRecord failed");
+  }
+  if (st == DMRG_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(DMRG_EHIP, "hipStreamSynchronize failed");
+  for (size_t i = 0; i < n && st == DMRG_OK; ++i)
+    if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess)
+      st = fail(DMRG_EHIP, "hipEventElapsedTime failed");
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
+dmrg_status dmrg_heff_diag(dmrg_heff_t h, double* diag) {
+  if (!h || !diag) return fail(DMRG_EINVAL, "heff_diag: bad arguments");
+  return launch_diag(h->d_dblocks, h->n_dblocks, h->d_ditems, h->lpool, h->rpool, diag,
+                     h->max_block_elems, h->ctx->stream);
+}
+
+dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const double* ybar,
+                                    double* psibar, double* left_pool_bar,
+                                    double* right_pool_bar) {
+  if (!h || !psi || !ybar) return fail(DMRG_EINVAL, "heff_apply_adjoint: bad arguments");
+  if (!psibar && !left_pool_bar && !right_pool_bar) return DMRG_OK;
+  const int want = (psibar ? 1 : 0) | (left_pool_bar ? 2 : 0) | (right_pool_bar ? 4 : 0);
+  if (!h->adj_built || h->adj_mask != want) {
+    h->adj.release();
+    if (h->adj_work) (void)hipFree(h->adj_work);
+    h->adj_work = nullptr;
+    h->adj_built = false;
+    h->adj_psibar = (want & 1) != 0;
+    h->adj_left = (want & 2) != 0;
+    h->adj_right = (want & 4) != 0;
+    dmrg_status st = build_adjoint(h, cfg_from_env());
+    if (st != DMRG_OK) return st;
+    {
+      int64_t len[BUF_COUNT] = {h->size, h->adj_psibar ? h->size : 0, h->llen, h->rlen,
+                                h->adj_work_elems, h->size, h->adj_left ? h->llen : 0,
+                                h->adj_right ? h->rlen : 0};
+      if ((st = h->adj.validate(len)) != DMRG_OK) return st;
+    }
+    if ((st = h->adj.upload()) != DMRG_OK) return st;
+    if (hipMalloc(&h->adj_work, h->adj_work_elems * sizeof(double)) != hipSuccess) {
+      h->adj_work = nullptr;
+      h->adj.release();
+      return fail(DMRG_ENOMEM, "heff_apply_adjoint: workspace allocation failed");
+    }
+    h->adj_built = true;
+    h->adj_mask = want;
+  }
+  Bases b{};
+  b.p[BUF_PSI] = const_cast<double*>(psi);
+  b.p[BUF_Y] = psibar;
+  b.p[BUF_LPOOL] = const_cast<double*>(h->lpool);
+  b.p[BUF_RPOOL] = const_cast<double*>(h->rpool);
+  b.p[BUF_WORK] = h->adj_work;
+  b.p[BUF_YBAR] = const_cast<double*>(ybar);
+  b.p[BUF_GL] = left_pool_bar;
+  b.p[BUF_GR] = right_pool_bar;
+  return h->adj.run(b, h->ctx->stream, DMRG_FP64);
+}
+
+}  // extern "C"
