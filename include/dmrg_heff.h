@@ -151,6 +151,15 @@ int64_t dmrg_heff_workspace_bytes(dmrg_heff_t h);
  * later applies with the same pointers (1) or launch eagerly (0). */
 dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable);
 
+/* Autotuner: times every tile shape (32x32, 64x64, 128x128) on the plan's
+ * own problems, grouped by phase (intermediates / output sums) and by the
+ * (M, N) size class (<=16, 32, 64, 128, 256, 512, larger), keeps the fastest
+ * shape per group and rebuilds the plan with it.  The timing runs the
+ * current precision's kernels on the context stream with psi and y (device
+ * double[size]; y and the workspace are overwritten).  reps >= 1 timed
+ * launches per candidate.  Synchronises. */
+dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps);
+
 /* Profiling: the matvec is a fixed sequence of grouped-GEMM launches.
  * n_launches (host) receives their number; when kernel / flops are non-null
  * (host arrays of at least that many entries) they receive each launch's
@@ -171,7 +180,9 @@ typedef struct {
   double tol;            /* stop when ||H x - theta x||_2 <= tol, ||x|| = 1  */
   int32_t fp64_tail;     /* split precision: iterations run in FP64 after the */
                          /* split-precision phase stalls (0 = none)           */
-  int32_t reserved;
+  int32_t start;         /* 0: start from the given vector; 1: from the unit  */
+                         /* vector at the lowest diagonal element (lowest     */
+                         /* index on ties), the given vector is ignored       */
 } dmrg_dav_opts;
 typedef struct {
   double energy;         /* Ritz value theta (Rayleigh quotient in FP64)     */
@@ -185,8 +196,9 @@ typedef struct {
 /* Davidson (E. R. Davidson 1975) for the lowest eigenpair of H_eff with the
  * diagonal preconditioner t = r / (theta - diag) (|theta - diag| clamped to
  * >= 1e-8), two-pass classical Gram-Schmidt, restart from the restart_keep
- * lowest Ritz vectors.  psi0 (device double[size], non-zero) is the start
- * vector.  Device memory: (2 * max_subspace + 8) * size doubles. */
+ * lowest Ritz vectors.  psi0 (device double[size], non-zero; may be NULL
+ * when opts->start = 1) is the start vector.  Device memory:
+ * (2 * max_subspace + 2 * restart_keep + 5) * size doubles. */
 dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts,
                                  const double* psi0, dmrg_dav_t* out);
 /* One iteration: Rayleigh-Ritz on the current subspace, residual, and (when

@@ -22,7 +22,7 @@ class Term(ctypes.Structure):
 class DavOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_int32), ("max_subspace", c_int32), ("restart_keep", c_int32),
                 ("use_graph", c_int32), ("tol", c_double), ("fp64_tail", c_int32),
-                ("reserved", c_int32)]
+                ("start", c_int32)]
 
 
 class DavResult(ctypes.Structure):
@@ -58,6 +58,7 @@ SIGNATURES = {
     "dmrg_heff_apply_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_heff_workspace_bytes": (c_int64, [c_void_p]),
     "dmrg_heff_use_graph": (c_int, [c_void_p, c_int32]),
+    "dmrg_heff_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_int32]),
     "dmrg_heff_launches": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int32), POINTER(c_double)]),
     "dmrg_heff_apply_profiled": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(ctypes.c_float)]),
     "dmrg_davidson_create": (c_int, [c_void_p, POINTER(DavOpts), c_void_p, POINTER(c_void_p)]),

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <vector>
 
 #include "plan.h"
 
@@ -358,6 +359,63 @@ __global__ void zero_kernel(double* __restrict__ b, int64_t n) {
     b[e] = 0.0;
 }
 
+// (value, index) of the smallest entry, lowest index on ties: per block into
+// partial[b*KMAX + {0,1}], then one block over the partials sets t = e_argmin.
+__device__ __forceinline__ bool less_vi(double v, double i, double w, double j) {
+  return v < w || (v == w && i < j);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void argmin_partial_kernel(const double* __restrict__ d,
+                                                                     int64_t n, double* __restrict__ partial) {
+  __shared__ double rv[RED_THREADS], ri[RED_THREADS];
+  double bv = INFINITY, bi = 1e300;
+  for (int64_t e = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; e < n; e += (int64_t)gridDim.x * RED_THREADS)
+    if (less_vi(d[e], (double)e, bv, bi)) {
+      bv = d[e];
+      bi = (double)e;
+    }
+  rv[threadIdx.x] = bv;
+  ri[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s && less_vi(rv[threadIdx.x + s], ri[threadIdx.x + s], rv[threadIdx.x], ri[threadIdx.x])) {
+      rv[threadIdx.x] = rv[threadIdx.x + s];
+      ri[threadIdx.x] = ri[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[(int64_t)blockIdx.x * KMAX] = rv[0];
+    partial[(int64_t)blockIdx.x * KMAX + 1] = ri[0];
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void argmin_finish_kernel(const double* __restrict__ partial,
+                                                                    int nblocks, int64_t n,
+                                                                    double* __restrict__ t) {
+  __shared__ double rv[RED_THREADS], ri[RED_THREADS];
+  double bv = INFINITY, bi = 1e300;
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+    if (less_vi(partial[(int64_t)b * KMAX], partial[(int64_t)b * KMAX + 1], bv, bi)) {
+      bv = partial[(int64_t)b * KMAX];
+      bi = partial[(int64_t)b * KMAX + 1];
+    }
+  rv[threadIdx.x] = bv;
+  ri[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s && less_vi(rv[threadIdx.x + s], ri[threadIdx.x + s], rv[threadIdx.x], ri[threadIdx.x])) {
+      rv[threadIdx.x] = rv[threadIdx.x + s];
+      ri[threadIdx.x] = ri[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t i = ri[0] < (double)n ? (int64_t)ri[0] : 0;  // all-NaN diagonal: first element
+    t[i] = 1.0;
+  }
+}
+
 // partial[b * KMAX] = sum over block b's elements of a[e] * b[e]
 __global__ __launch_bounds__(RED_THREADS) void scalar_dot_kernel(const double* __restrict__ a,
                                                                  const double* __restrict__ b, int64_t n,
@@ -508,7 +566,8 @@ dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts, const
                                  dmrg_dav_t* out) {
   if (!out) return fail(DMRG_EINVAL, "davidson_create: out is NULL");
   *out = nullptr;
-  if (!h || !opts || !psi0) return fail(DMRG_EINVAL, "davidson_create: bad arguments");
+  if (!h || !opts || (!psi0 && opts->start != 1) || opts->start < 0 || opts->start > 1)
+    return fail(DMRG_EINVAL, "davidson_create: bad arguments");
   const dmrg_dav_opts& o = *opts;
   if (o.max_subspace < 2 || o.max_subspace > KMAX || o.restart_keep < 1 ||
       o.restart_keep >= o.max_subspace || o.max_iter < 0 || !(o.tol >= 0.0) || o.fp64_tail < 0)
@@ -555,8 +614,14 @@ dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts, const
   set_state_kernel<<<1, 1, 0, s>>>(d->st, 0);
   dmrg_status st = dmrg_heff_diag(h, d->diag);
   if (st != DMRG_OK) return st;
-  // first basis vector: psi0 / ||psi0||
-  copy_kernel<<<g, 256, 0, s>>>(psi0, n, d->t);
+  // first basis vector: psi0 / ||psi0||, or the unit vector at argmin diag
+  if (o.start == 1) {
+    zero_kernel<<<g, 256, 0, s>>>(d->t, n);
+    argmin_partial_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(d->diag, n, d->partial);
+    argmin_finish_kernel<<<1, RED_THREADS, 0, s>>>(d->partial, RED_BLOCKS, n, d->t);
+  } else {
+    copy_kernel<<<g, 256, 0, s>>>(psi0, n, d->t);
+  }
   scalar_dot_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(d->t, d->t, n, d->partial);
   finish_scalar_kernel<<<1, RED_THREADS, 0, s>>>(d->partial, RED_BLOCKS, d->dots);
   normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, n, d->t);
@@ -607,16 +672,22 @@ dmrg_status dmrg_davidson_vector(dmrg_dav_t d, double* x) {
 
 void dmrg_davidson_destroy(dmrg_dav_t d) { free_dav(d); }
 
-dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts,
-                          dmrg_dav_result* res) {
-  if (!h || !psi_inout || !opts || !res) return fail(DMRG_EINVAL, "davidson: bad arguments");
+}  // extern "C"
+
+namespace {
+
+// One Davidson run from psi_inout; stop_early(res) may end it before
+// convergence (used to leave the split-precision phase once it stalls).
+template <class Stop>
+dmrg_status solve(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts, dmrg_dav_result* res,
+                  Stop&& stop_early) {
   dmrg_dav_t d = nullptr;
   dmrg_status st = dmrg_davidson_create(h, opts, psi_inout, &d);
   if (st != DMRG_OK) return st;
   std::memset(res, 0, sizeof(*res));
   while (true) {
     st = dmrg_davidson_step(d, res);
-    if (st != DMRG_OK || res->converged) break;
+    if (st != DMRG_OK || res->converged || stop_early(*res)) break;
   }
   dmrg_status st2 = dmrg_davidson_vector(d, psi_inout);
   if (st == DMRG_OK) st = st2;
@@ -626,4 +697,34 @@ dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts*
   return st;
 }
 
-}  // extern "C"
+}  // namespace
+
+extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts,
+                          dmrg_dav_result* res) {
+  if (!h || !psi_inout || !opts || !res) return fail(DMRG_EINVAL, "davidson: bad arguments");
+  if (h->prec != DMRG_SPLIT_BF16X3 || opts->fp64_tail <= 0)
+    return solve(h, psi_inout, opts, res, [](const dmrg_dav_result&) { return false; });
+  // Split-precision phase: iterate while the residual keeps falling (it
+  // levels off near the matvec's own error), then an FP64 tail restarted from
+  // that Ritz vector brings the residual, the energy and the vector to the
+  // FP64 tolerance.
+  std::vector<double> hist;
+  dmrg_dav_result r1{};
+  dmrg_status st = solve(h, psi_inout, opts, &r1, [&](const dmrg_dav_result& r) {
+    hist.push_back(r.residual);
+    const size_t n = hist.size();
+    return n >= 4 && hist[n - 1] > 0.5 * hist[n - 4];
+  });
+  if (st != DMRG_OK && st != DMRG_ENOCONV) return st;
+  dmrg_dav_opts o2 = *opts;
+  o2.max_iter = opts->fp64_tail;
+  h->prec = DMRG_FP64;
+  dmrg_dav_result r2{};
+  st = solve(h, psi_inout, &o2, &r2, [](const dmrg_dav_result&) { return false; });
+  h->prec = DMRG_SPLIT_BF16X3;
+  *res = r2;
+  res->iters = r1.iters + r2.iters;
+  res->matvecs = r1.matvecs + r2.matvecs;
+  res->tail_iters = r2.iters;
+  return st;
+}

@@ -9,9 +9,16 @@
 // walks all of its segments in order, so every sum is computed in a fixed
 // order by one workgroup: no atomics, bit-reproducible results.
 //
+// Pipelining: the (segment, K tile) sequence of a tile is walked as one flat
+// stream; the global loads of the next K tile are issued into registers
+// before the matrix-core work on the current LDS buffer, and land in the other
+// LDS buffer afterwards, so one barrier separates consecutive K tiles.
+//
 // Matrix core: v_mfma_f64_16x16x4_f64.  Operand lanes: A[i][k] comes from lane
 // i + 16k, B[k][j] from lane j + 16k; the four result doubles of lane l hold
 // D[l/16 + 4v][l%16], v = 0..3 (measured on gfx950).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace dmrg {
@@ -27,6 +34,74 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// Registers holding one K tile of X (BM x BK) and Z (BK x BN) in flight.
+template <int BM, int BN, int BK, int NT>
+struct TileRegs {
+  static constexpr int NX = (BM * BK + NT - 1) / NT;
+  static constexpr int NZ = (BN * BK + NT - 1) / NT;
+  double x[NX];
+  double z[NZ];
+
+  __device__ __forceinline__ void load(const Seg& g, const double* __restrict__ X,
+                                       const double* __restrict__ Z, int k0, int m0, int n0, int M,
+                                       int N, int tid) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      const int i = tid + r * NT;
+      int mm, kk;
+      if (!g.xt) {
+        mm = i / BK;
+        kk = i % BK;
+      } else {
+        mm = i % BM;
+        kk = i / BM;
+      }
+      const int m = m0 + mm, k = k0 + kk;
+      const bool ok = i < BM * BK && m < M && k < g.K;
+      x[r] = ok ? X[g.xt ? (int64_t)k * g.ldx + m : (int64_t)m * g.ldx + k] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < NZ; ++r) {
+      const int i = tid + r * NT;
+      int nn, kk;
+      if (!g.zt) {
+        nn = i % BN;
+        kk = i / BN;
+      } else {
+        nn = i / BK;
+        kk = i % BK;
+      }
+      const int n = n0 + nn, k = k0 + kk;
+      const bool ok = i < BN * BK && n < N && k < g.K;
+      z[r] = ok ? Z[g.zt ? (int64_t)n * g.ldz + k : (int64_t)k * g.ldz + n] : 0.0;
+    }
+  }
+
+  __device__ __forceinline__ void store(const Seg& g, double alpha, double (*Xs)[BM + 1],
+                                        double (*Zs)[BN + 1], int tid) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      const int i = tid + r * NT;
+      if (i < BM * BK) {
+        if (!g.xt)
+          Xs[i % BK][i / BK] = alpha * x[r];
+        else
+          Xs[i / BM][i % BM] = alpha * x[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NZ; ++r) {
+      const int i = tid + r * NT;
+      if (i < BN * BK) {
+        if (!g.zt)
+          Zs[i / BN][i % BN] = z[r];
+        else
+          Zs[i % BK][i / BK] = z[r];
+      }
+    }
+  }
+};
+
 template <int BM, int BN, int BK, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
     Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
@@ -35,8 +110,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   static_assert(FM >= 1 && FN >= 1 && BK % 4 == 0, "tile shape");
-  __shared__ double Xs[BK][BM + 1];
-  __shared__ double Zs[BK][BN + 1];
+  __shared__ double Xs[2][BK][BM + 1];
+  __shared__ double Zs[2][BK][BN + 1];
 
   const int64_t lt = xcd_remap(blockIdx.x, ntiles);
   const Tile t = tiles[lt];
@@ -53,59 +128,49 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int s = p.seg0; s < p.seg0 + p.nseg; ++s) {
-    const Seg g = segs[s];
-    const double* __restrict__ X = bases.p[g.xbuf] + g.xoff;
-    const double* __restrict__ Z = bases.p[g.zbuf] + g.zoff;
-    const double alpha = g.alpha;
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-      // X tile (BM x BK) -> Xs[k][m]
-      if (!g.xt) {
-#pragma unroll
-        for (int i = tid; i < BM * BK; i += NT) {
-          const int mm = i / BK, kk = i % BK;
-          const int m = m0 + mm, k = k0 + kk;
-          Xs[kk][mm] = (m < p.M && k < g.K) ? alpha * X[(int64_t)m * g.ldx + k] : 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int i = tid; i < BM * BK; i += NT) {
-          const int mm = i % BM, kk = i / BM;
-          const int m = m0 + mm, k = k0 + kk;
-          Xs[kk][mm] = (m < p.M && k < g.K) ? alpha * X[(int64_t)k * g.ldx + m] : 0.0;
-        }
+  const int s_end = p.seg0 + p.nseg;
+  if (p.nseg > 0) {
+    TileRegs<BM, BN, BK, NT> regs;
+    int s = p.seg0, k0 = 0;
+    Seg g = segs[s];
+    regs.load(g, bases.p[g.xbuf] + g.xoff, bases.p[g.zbuf] + g.zoff, 0, m0, n0, p.M, p.N, tid);
+    regs.store(g, g.alpha, Xs[0], Zs[0], tid);
+    __syncthreads();
+    int buf = 0;
+    while (true) {
+      // next (segment, K tile) position
+      int s2 = s, k2 = k0 + BK;
+      Seg g2 = g;
+      if (k2 >= g.K) {
+        ++s2;
+        k2 = 0;
+        if (s2 < s_end) g2 = segs[s2];
       }
-      // Z tile (BK x BN) -> Zs[k][n]
-      if (!g.zt) {
-#pragma unroll
-        for (int i = tid; i < BK * BN; i += NT) {
-          const int nn = i % BN, kk = i / BN;
-          const int n = n0 + nn, k = k0 + kk;
-          Zs[kk][nn] = (n < p.N && k < g.K) ? Z[(int64_t)k * g.ldz + n] : 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int i = tid; i < BK * BN; i += NT) {
-          const int kk = i % BK, nn = i / BK;
-          const int n = n0 + nn, k = k0 + kk;
-          Zs[kk][nn] = (n < p.N && k < g.K) ? Z[(int64_t)n * g.ldz + k] : 0.0;
-        }
-      }
-      __syncthreads();
+      const bool more = s2 < s_end;
+      if (more)
+        regs.load(g2, bases.p[g2.xbuf] + g2.xoff, bases.p[g2.zbuf] + g2.zoff, k2, m0, n0, p.M, p.N,
+                  tid);
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         double a[FM], b[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) a[i] = Xs[kk + fk][wm * WM + i * 16 + fr];
+        for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kk + fk][wm * WM + i * 16 + fr];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) b[j] = Zs[kk + fk][wn * WN + j * 16 + fr];
+        for (int j = 0; j < FN; ++j) b[j] = Zs[buf][kk + fk][wn * WN + j * 16 + fr];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       }
+      if (!more) break;
+      // the other buffer was last read before the previous barrier
+      regs.store(g2, g2.alpha, Xs[buf ^ 1], Zs[buf ^ 1], tid);
       __syncthreads();
+      buf ^= 1;
+      s = s2;
+      k0 = k2;
+      g = g2;
     }
   }
 
@@ -131,6 +196,7 @@ int cfg_bn(int cfg) { return cfg_bm(cfg); }
 dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                         const Tile* tiles, hipStream_t s) {
   if (l.ntiles <= 0) return DMRG_OK;
+  if (l.split) return launch_gemm_split(l, b, probs, segs, tiles, s);
   const Tile* t = tiles + l.tile0;
   dim3 grid((unsigned)l.ntiles);
   switch (l.cfg) {
@@ -182,6 +248,36 @@ dmrg_status launch_diag(const DiagBlock* blocks, int nblocks, const DiagItem* it
   if (gx < 1) gx = 1;
   diag_kernel<<<dim3((unsigned)gx, (unsigned)nblocks), 256, 0, s>>>(blocks, nblocks, items, lpool,
                                                                      rpool, out);
+  DMRG_HIP(hipGetLastError());
+  return DMRG_OK;
+}
+
+}  // namespace dmrg
+
+namespace dmrg {
+
+// C += sum of its partials, in part order (deterministic).
+__global__ void reduce_kernel(Bases b, const RedBlock* __restrict__ reds, int r0,
+                              const int64_t* __restrict__ parts) {
+  const RedBlock r = reds[r0 + blockIdx.y];
+  double* __restrict__ C = b.p[r.cbuf] + r.coff;
+  const double* __restrict__ P = b.p[BUF_PART];
+  const int64_t n = (int64_t)r.M * r.N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / r.N, j = e % r.N;
+    double acc = C[i * r.ldc + j];
+    for (int k = 0; k < r.nparts; ++k) acc += P[parts[r.part0 + k] + e];
+    C[i * r.ldc + j] = acc;
+  }
+}
+
+dmrg_status launch_reduce(const Launch& l, const Bases& b, const RedBlock* reds,
+                          const int64_t* parts, hipStream_t s) {
+  for (int64_t r0 = l.tile0; r0 < l.tile0 + l.ntiles; r0 += 65535) {
+    const int64_t n = std::min<int64_t>(65535, l.tile0 + l.ntiles - r0);
+    reduce_kernel<<<dim3(32, (unsigned)n), 256, 0, s>>>(b, reds, (int)r0, parts);
+  }
   DMRG_HIP(hipGetLastError());
   return DMRG_OK;
 }

@@ -47,6 +47,8 @@ dmrg_status Program::upload() {
   if ((st = put(probs, &d_probs)) != DMRG_OK) return st;
   if ((st = put(segs, &d_segs)) != DMRG_OK) return st;
   if ((st = put(tiles, &d_tiles)) != DMRG_OK) return st;
+  if ((st = put(reds, &d_reds)) != DMRG_OK) return st;
+  if ((st = put(red_parts, &d_red_parts)) != DMRG_OK) return st;
   return DMRG_OK;
 }
 
@@ -74,7 +76,22 @@ dmrg_status Program::validate(const int64_t* len) const {
         return fail(DMRG_EQN, "plan: operand of problem " + std::to_string(pi) + " out of bounds");
     }
   }
+  for (size_t ri = 0; ri < reds.size(); ++ri) {
+    const RedBlock& r = reds[ri];
+    if (r.M < 1 || r.N < 1 || r.ldc < r.N || r.part0 < 0 || r.nparts < 1 ||
+        (size_t)r.part0 + r.nparts > red_parts.size() ||
+        !in(r.cbuf, r.coff, r.coff + (int64_t)(r.M - 1) * r.ldc + r.N - 1))
+      return fail(DMRG_EQN, "plan: malformed reduction " + std::to_string(ri));
+    for (int k = 0; k < r.nparts; ++k)
+      if (!in(BUF_PART, red_parts[r.part0 + k], red_parts[r.part0 + k] + (int64_t)r.M * r.N - 1))
+        return fail(DMRG_EQN, "plan: partial of reduction " + std::to_string(ri) + " out of bounds");
+  }
   for (const Launch& l : launches) {
+    if (l.cfg == CFG_REDUCE) {
+      if (l.tile0 < 0 || l.ntiles < 1 || l.tile0 + l.ntiles > (int64_t)reds.size())
+        return fail(DMRG_EQN, "plan: reduction launch outside its table");
+      continue;
+    }
     if (l.tile0 < 0 || l.ntiles < 0 || l.tile0 + l.ntiles > (int64_t)tiles.size())
       return fail(DMRG_EQN, "plan: launch outside the tile table");
     const int bm = cfg_bm(l.cfg), bn = cfg_bn(l.cfg);
@@ -93,18 +110,31 @@ void Program::release() {
   if (d_segs) (void)hipFree(d_segs);
   if (d_tiles) (void)hipFree(d_tiles);
   d_probs = nullptr;
+  if (d_reds) (void)hipFree(d_reds);
+  if (d_red_parts) (void)hipFree(d_red_parts);
   d_segs = nullptr;
   d_tiles = nullptr;
+  d_reds = nullptr;
+  d_red_parts = nullptr;
 }
 
 dmrg_status Program::run(const Bases& b, hipStream_t s, int precision) const {
   for (const Launch& l : launches) {
     Launch x = l;
     x.split = precision;
-    dmrg_status st = launch_gemm(x, b, d_probs, d_segs, d_tiles, s);
+    dmrg_status st = l.cfg == CFG_REDUCE ? launch_reduce(x, b, d_reds, d_red_parts, s)
+                                         : launch_gemm(x, b, d_probs, d_segs, d_tiles, s);
     if (st != DMRG_OK) return st;
   }
   return DMRG_OK;
+}
+
+// K length above which output sums are cut (DMRG_HEFF_KCHUNK overrides the
+// default, for tests).
+int64_t kchunk_from_env() {
+  const char* s = std::getenv("DMRG_HEFF_KCHUNK");
+  const int64_t v = s ? std::atoll(s) : KCHUNK;
+  return v >= 16 ? v : KCHUNK;
 }
 
 // Tile shape for one output matrix.
@@ -117,10 +147,58 @@ int choose_cfg(int M, int N) {
 // Appends the tiles of `probs[first..)` grouped by tile configuration, one
 // launch per configuration.
 void ProgramBuilder::close_phase() {
+  // cut long-K problems into parts of about kchunk along segment boundaries
+  const int64_t kchunk = kchunk_from_env();
+  const size_t nprob = prog.probs.size();
+  const size_t red_first = prog.reds.size();
+  int64_t part_used = 0;
+  for (size_t pi = phase_first; pi < nprob; ++pi) {
+    Prob p = prog.probs[pi];
+    int64_t ktot = 0;
+    for (int s = p.seg0; s < p.seg0 + p.nseg; ++s) ktot += prog.segs[s].K;
+    if (p.nseg < 2 || ktot <= kchunk) continue;
+    const int64_t nparts = std::min<int64_t>((ktot + kchunk - 1) / kchunk, p.nseg);
+    const double target = (double)ktot / (double)nparts;
+    std::vector<int32_t> cut{p.seg0};
+    int64_t acc = 0;
+    for (int s = p.seg0; s < p.seg0 + p.nseg; ++s) {
+      acc += prog.segs[s].K;
+      if (acc >= target * (double)cut.size() && (int64_t)cut.size() < nparts && s + 1 < p.seg0 + p.nseg)
+        cut.push_back(s + 1);
+    }
+    cut.push_back(p.seg0 + p.nseg);
+    if (cut.size() <= 2) continue;
+    RedBlock r{};
+    r.coff = p.coff;
+    r.M = p.M;
+    r.N = p.N;
+    r.ldc = p.ldc;
+    r.cbuf = p.cbuf;
+    r.part0 = (int32_t)prog.red_parts.size();
+    r.nparts = (int32_t)cut.size() - 2;
+    prog.probs[pi].nseg = cut[1] - cut[0];
+    for (size_t c = 1; c + 1 < cut.size(); ++c) {
+      Prob q = p;
+      q.cbuf = BUF_PART;
+      q.coff = part_used;
+      q.ldc = p.N;
+      q.beta = 0;
+      q.seg0 = cut[c];
+      q.nseg = cut[c + 1] - cut[c];
+      prog.red_parts.push_back(part_used);
+      part_used += (int64_t)p.M * p.N;
+      prog.probs.push_back(q);
+    }
+    prog.reds.push_back(r);
+  }
+  prog.part_elems = std::max(prog.part_elems, part_used);
   std::vector<std::vector<Tile>> per(CFG_F64_COUNT);
   for (size_t pi = phase_first; pi < prog.probs.size(); ++pi) {
     const Prob& p = prog.probs[pi];
-    int cfg = cfg_override >= 0 ? cfg_override : choose_cfg(p.M, p.N);
+    int cfg = cfg_override;
+    if (cfg < 0 && tune) cfg = tune->cfg[phase_id][size_bucket(p.M)][size_bucket(p.N)];
+    if (cfg < 0) cfg = choose_cfg(p.M, p.N);
+    prog.probs[pi].pad0 = (uint8_t)phase_id;
     int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
     int tm = (p.M + bm - 1) / bm, tn = (p.N + bn - 1) / bn;
     for (int i = 0; i < tm; ++i)
@@ -132,6 +210,8 @@ void ProgramBuilder::close_phase() {
     prog.tiles.insert(prog.tiles.end(), per[c].begin(), per[c].end());
     prog.launches.push_back(l);
   }
+  if (prog.reds.size() > red_first)
+    prog.launches.push_back(Launch{CFG_REDUCE, 0, (int64_t)red_first, (int64_t)(prog.reds.size() - red_first)});
   phase_first = prog.probs.size();
 }
 

@@ -35,7 +35,8 @@ enum BufId : uint8_t {
   BUF_YBAR = 5,   // upstream gradient (adjoint)
   BUF_GL = 6,     // left pool gradient (adjoint)
   BUF_GR = 7,     // right pool gradient (adjoint)
-  BUF_COUNT = 8
+  BUF_PART = 8,   // partial sums of split long-K problems
+  BUF_COUNT = 9
 };
 struct Bases {
   double* p[BUF_COUNT];
@@ -78,7 +79,9 @@ enum TileCfg : int32_t {
 int cfg_bm(int cfg);
 int cfg_bn(int cfg);
 
-// A launch of the grouped GEMM over a contiguous range of the tile table.
+// A launch of the grouped GEMM over a contiguous range of the tile table, or
+// (cfg == CFG_REDUCE) of the reduction over a range of the RedBlock table.
+constexpr int32_t CFG_REDUCE = 100;
 struct Launch {
   int32_t cfg;
   int32_t split;     // 0 FP64, 1 split BF16x3
@@ -86,15 +89,35 @@ struct Launch {
   int64_t ntiles;
 };
 
+// Long-K problems are cut into K parts that run as separate workgroups: part
+// 0 writes the real output, the others write dense partials, and the
+// reduction adds the partials to the output in part order (deterministic).
+struct RedBlock {
+  int64_t coff;    // output offset (in buffer cbuf), dense M x N with row stride ldc
+  int32_t M, N, ldc;
+  int32_t part0;   // first index into the part-offset table
+  int32_t nparts;  // partials to add
+  uint8_t cbuf, pad0, pad1, pad2;
+};
+
+// K length above which an output problem is cut into parts (a fixed
+// constant, so the cut does not depend on the tile shape).
+constexpr int64_t KCHUNK = 4096;
+
 // A program: ordered launches over one set of device tables.
 struct Program {
   std::vector<Prob> probs;
   std::vector<Seg> segs;
   std::vector<Tile> tiles;
   std::vector<Launch> launches;
+  std::vector<RedBlock> reds;
+  std::vector<int64_t> red_parts;  // offsets of partials in BUF_PART
+  int64_t part_elems = 0;          // BUF_PART doubles needed
   Prob* d_probs = nullptr;
   Seg* d_segs = nullptr;
   Tile* d_tiles = nullptr;
+  RedBlock* d_reds = nullptr;
+  int64_t* d_red_parts = nullptr;
   dmrg_status upload();
   void release();
   // Host-side bounds proof of every access the kernels will make, given the
@@ -105,6 +128,10 @@ struct Program {
 
 dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                         const Tile* tiles, hipStream_t s);
+dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
+                              const Tile* tiles, hipStream_t s);
+dmrg_status launch_reduce(const Launch& l, const Bases& b, const RedBlock* reds,
+                          const int64_t* parts, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Diagonal: per wavefunction block, the dq = 0 pairs that reach it.

@@ -29,10 +29,26 @@ struct Item {
   double alpha;
 };
 
+// Tile configuration per (phase, M bucket, N bucket); -1 = built-in rule.
+constexpr int TUNE_BUCKETS = 7;
+inline int size_bucket(int x) {
+  return x <= 16 ? 0 : x <= 32 ? 1 : x <= 64 ? 2 : x <= 128 ? 3 : x <= 256 ? 4 : x <= 512 ? 5 : 6;
+}
+struct TuneTable {
+  int8_t cfg[2][TUNE_BUCKETS][TUNE_BUCKETS];
+  TuneTable() {
+    for (auto& a : cfg)
+      for (auto& b : a)
+        for (auto& c : b) c = -1;
+  }
+};
+
 struct ProgramBuilder {
   Program prog;
   size_t phase_first = 0;
   int cfg_override = -1;
+  int phase_id = 0;                 // 0: intermediates, 1: sums into the outputs
+  const TuneTable* tune = nullptr;
   int32_t add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta);
   void add_seg(int32_t prob, const Seg& s);
   void close_phase();
@@ -59,9 +75,12 @@ struct dmrg_heff_s {
   int64_t llen = 0, rlen = 0;
   double flops = 0.0, bytes = 0.0;
   int prec = DMRG_FP64;
+  dmrg::TuneTable tune;     // tile shape per (phase, size bucket)
   int64_t work_budget = 0;  // doubles
   double* work = nullptr;
   int64_t work_elems = 0;
+  double* part = nullptr;      // partials of cut long-K sums (forward)
+  double* adj_part = nullptr;  // the same for the adjoint
   dmrg::Program fwd;
   dmrg::Program adj;
   bool adj_built = false;

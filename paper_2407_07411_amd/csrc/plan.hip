@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <memory>
 #include <new>
 #include <set>
@@ -17,7 +18,7 @@ namespace {
 
 int64_t env_workspace_doubles() {
   const char* s = std::getenv("DMRG_HEFF_WORKSPACE_MB");
-  int64_t mb = s ? std::atoll(s) : 2048;
+  int64_t mb = s ? std::atoll(s) : 8192;
   if (mb < 1) mb = 1;
   return mb * (1 << 20) / 8;
 }
@@ -189,87 +190,82 @@ void opBt_as_z(const Item& it, bool* zt, int* ldz) {
 
 // Forward program: phase 1 computes T = alpha op(A) X (left-first) or
 // W = alpha X op(B)^T (right-first) for the wave's two-sided items; phase 2
-// writes each output block once per wave as a long-K sum.
+// adds each output block's intermediates as one long-K sum.  Waves are
+// contiguous ranges of the item list, which is in term order, so every wave
+// reaches most output blocks and its output sums span the whole of Y (many
+// tiles); long sums are cut into K parts by the builder.
 dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
+  pb.tune = &h->tune;
   const int nb = (int)h->blocks.size();
-  std::vector<std::vector<int32_t>> by_out(nb);
-  for (size_t i = 0; i < h->items.size(); ++i) by_out[h->items[i].out].push_back((int32_t)i);
-  std::vector<uint8_t> written(nb, 0);
-  std::vector<double> lf_first(h->items.size());
+  const size_t ni = h->items.size();
+  std::vector<uint8_t> lf_first(ni, 1), reached(nb, 0), written(nb, 0);
+  std::vector<int64_t> need(ni, 0), woff(ni, 0);
   int64_t max_need = 0;
-  for (size_t i = 0; i < h->items.size(); ++i) {
+  for (size_t i = 0; i < ni; ++i) {
     const Item& it = h->items[i];
+    reached[it.out] = 1;
     if (it.kind != 0) continue;
     double lf, rf;
     item_costs(h, it, &lf, &rf);
-    lf_first[i] = lf <= rf ? 1.0 : 0.0;
+    lf_first[i] = lf <= rf ? 1 : 0;
     const BlockInfo& bi = h->blocks[it.in];
     const BlockInfo& bo = h->blocks[it.out];
-    int64_t need = lf_first[i] ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
-    max_need = std::max(max_need, need);
+    need[i] = lf_first[i] ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
+    max_need = std::max(max_need, need[i]);
   }
   const int64_t budget = std::max(h->work_budget, max_need);
-  // waves over output blocks (items of one block stay together when possible)
-  struct Wave {
-    std::vector<std::pair<int32_t, int64_t>> items;  // item, workspace offset
-  };
-  std::vector<Wave> waves(1);
+  std::vector<std::pair<size_t, size_t>> waves;
+  size_t w0 = 0;
   int64_t used = 0, peak = 0;
-  for (int ob = 0; ob < nb; ++ob) {
-    for (int32_t ii : by_out[ob]) {
-      const Item& it = h->items[ii];
-      int64_t need = 0;
-      if (it.kind == 0) {
-        const BlockInfo& bi = h->blocks[it.in];
-        const BlockInfo& bo = h->blocks[it.out];
-        need = lf_first[ii] ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
-      }
-      if (used + need > budget && !waves.back().items.empty()) {
-        waves.emplace_back();
-        used = 0;
-      }
-      waves.back().items.push_back({ii, used});
-      used += need;
-      peak = std::max(peak, used);
+  for (size_t i = 0; i < ni; ++i) {
+    if (used + need[i] > budget && i > w0) {
+      waves.push_back({w0, i});
+      w0 = i;
+      used = 0;
     }
+    woff[i] = used;
+    used += need[i];
+    peak = std::max(peak, used);
   }
+  waves.push_back({w0, ni});
   h->work_elems = std::max<int64_t>(peak, 1);
   for (size_t w = 0; w < waves.size(); ++w) {
     // phase 1
-    for (auto& pr : waves[w].items) {
-      const Item& it = h->items[pr.first];
+    for (size_t i = waves[w].first; i < waves[w].second; ++i) {
+      const Item& it = h->items[i];
       if (it.kind != 0) continue;
       const BlockInfo& bi = h->blocks[it.in];
       const BlockInfo& bo = h->blocks[it.out];
       bool xt, zt;
       int ldx, ldz;
-      if (lf_first[pr.first]) {
-        int32_t p = pb.add_prob(BUF_WORK, pr.second, bo.dl, bi.dr, bi.dr, false);
+      if (lf_first[i]) {
+        int32_t p = pb.add_prob(BUF_WORK, woff[i], bo.dl, bi.dr, bi.dr, false);
         opA_as_x(it, &xt, &ldx);
         pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
                                it.alpha));
       } else {
-        int32_t p = pb.add_prob(BUF_WORK, pr.second, bi.dl, bo.dr, bo.dr, false);
+        int32_t p = pb.add_prob(BUF_WORK, woff[i], bi.dl, bo.dr, bo.dr, false);
         opBt_as_z(it, &zt, &ldz);
         pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt, bi.dr,
                                it.alpha));
       }
     }
+    pb.phase_id = 0;
     pb.close_phase();
     // phase 2: one problem per output block present in the wave
-    std::map<int32_t, std::vector<std::pair<int32_t, int64_t>>> per_out;
-    for (auto& pr : waves[w].items) per_out[h->items[pr.first].out].push_back(pr);
+    std::map<int32_t, std::vector<size_t>> per_out;
+    for (size_t i = waves[w].first; i < waves[w].second; ++i) per_out[h->items[i].out].push_back(i);
     if (w == 0)
       for (int ob = 0; ob < nb; ++ob)
-        if (by_out[ob].empty()) per_out[ob];  // blocks nothing reaches are written as zeros
+        if (!reached[ob]) per_out[ob];  // blocks nothing reaches are written as zeros
     for (auto& kv : per_out) {
       const BlockInfo& bo = h->blocks[kv.first];
       int32_t p = pb.add_prob(BUF_Y, bo.off, bo.dl, bo.dr, bo.dr, written[kv.first] != 0);
       written[kv.first] = 1;
-      for (auto& pr : kv.second) {
-        const Item& it = h->items[pr.first];
+      for (size_t i : kv.second) {
+        const Item& it = h->items[i];
         const BlockInfo& bi = h->blocks[it.in];
         bool xt, zt;
         int ldx, ldz;
@@ -281,17 +277,18 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
           opBt_as_z(it, &zt, &ldz);
           pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt, bi.dr,
                                  it.alpha));
-        } else if (lf_first[pr.first]) {
+        } else if (lf_first[i]) {
           opBt_as_z(it, &zt, &ldz);
-          pb.add_seg(p, make_seg(BUF_WORK, pr.second, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt,
+          pb.add_seg(p, make_seg(BUF_WORK, woff[i], bi.dr, false, BUF_RPOOL, it.boff, ldz, zt,
                                  bi.dr, 1.0));
         } else {
           opA_as_x(it, &xt, &ldx);
-          pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_WORK, pr.second, bo.dr, false,
+          pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_WORK, woff[i], bo.dr, false,
                                  bi.dl, 1.0));
         }
       }
     }
+    pb.phase_id = 1;
     pb.close_phase();
   }
   h->fwd = std::move(pb.prog);
@@ -307,6 +304,7 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
 dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
+  pb.tune = &h->tune;
   const int64_t nitems = (int64_t)h->items.size();
   std::vector<int64_t> woff(nitems, -1);
   int64_t budget = std::max<int64_t>(h->work_budget, 1);
@@ -490,6 +488,7 @@ Bases fwd_bases(dmrg_heff_s* h, const double* psi, double* y) {
   b.p[BUF_LPOOL] = const_cast<double*>(h->lpool);
   b.p[BUF_RPOOL] = const_cast<double*>(h->rpool);
   b.p[BUF_WORK] = h->work;
+  b.p[BUF_PART] = h->part;
   return b;
 }
 
@@ -551,10 +550,16 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   h->work_budget = env_workspace_doubles();
   if ((st = build_forward(h.get(), cfg_from_env())) != DMRG_OK) return st;
   {
-    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0};
+    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0,
+                              h->fwd.part_elems};
     if ((st = h->fwd.validate(len)) != DMRG_OK) return st;
   }
   if ((st = h->fwd.upload()) != DMRG_OK) return st;
+  if (hipMalloc(&h->part, std::max<int64_t>(h->fwd.part_elems, 1) * sizeof(double)) != hipSuccess) {
+    h->part = nullptr;
+    h->fwd.release();
+    return fail(DMRG_ENOMEM, "heff_create: partial-sum buffer allocation failed");
+  }
   if (hipMalloc(&h->work, h->work_elems * sizeof(double)) != hipSuccess) {
     h->work = nullptr;
     h->fwd.release();
@@ -576,6 +581,8 @@ void dmrg_heff_destroy(dmrg_heff_t h) {
   h->adj.release();
   if (h->work) (void)hipFree(h->work);
   if (h->adj_work) (void)hipFree(h->adj_work);
+  if (h->part) (void)hipFree(h->part);
+  if (h->adj_part) (void)hipFree(h->adj_part);
   if (h->d_dblocks) (void)hipFree(h->d_dblocks);
   if (h->d_ditems) (void)hipFree(h->d_ditems);
   delete h;
@@ -642,8 +649,10 @@ dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kern
   *n_launches = (int64_t)P.launches.size();
   for (size_t i = 0; i < P.launches.size(); ++i) {
     const Launch& l = P.launches[i];
-    if (kernel) kernel[i] = l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : 0);
-    if (flops) {
+    if (kernel) kernel[i] = l.cfg == CFG_REDUCE ? 3 : l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : 0);
+    if (flops && l.cfg == CFG_REDUCE) {
+      flops[i] = 0.0;
+    } else if (flops) {
       double f = 0.0;
       int64_t last = -1;
       for (int64_t t = l.tile0; t < l.tile0 + l.ntiles; ++t) {
@@ -673,7 +682,8 @@ dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y
   for (size_t i = 0; i < n && st == DMRG_OK; ++i) {
     Launch x = P.launches[i];
     x.split = h->prec;
-    st = launch_gemm(x, b, P.d_probs, P.d_segs, P.d_tiles, s);
+    st = x.cfg == CFG_REDUCE ? launch_reduce(x, b, P.d_reds, P.d_red_parts, s)
+                             : launch_gemm(x, b, P.d_probs, P.d_segs, P.d_tiles, s);
     if (st == DMRG_OK && hipEventRecord(ev[i + 1], s) != hipSuccess)
       st = fail(DMRG_EHIP, "hipEventRecord failed");
   }
@@ -711,8 +721,14 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
     {
       int64_t len[BUF_COUNT] = {h->size, h->adj_psibar ? h->size : 0, h->llen, h->rlen,
                                 h->adj_work_elems, h->size, h->adj_left ? h->llen : 0,
-                                h->adj_right ? h->rlen : 0};
+                                h->adj_right ? h->rlen : 0, h->adj.part_elems};
       if ((st = h->adj.validate(len)) != DMRG_OK) return st;
+    }
+    if (h->adj_part) (void)hipFree(h->adj_part);
+    if (hipMalloc(&h->adj_part, std::max<int64_t>(h->adj.part_elems, 1) * sizeof(double)) != hipSuccess) {
+      h->adj_part = nullptr;
+      h->adj.release();
+      return fail(DMRG_ENOMEM, "heff_apply_adjoint: partial-sum buffer allocation failed");
     }
     if ((st = h->adj.upload()) != DMRG_OK) return st;
     if (hipMalloc(&h->adj_work, h->adj_work_elems * sizeof(double)) != hipSuccess) {
@@ -732,7 +748,100 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
   b.p[BUF_YBAR] = const_cast<double*>(ybar);
   b.p[BUF_GL] = left_pool_bar;
   b.p[BUF_GR] = right_pool_bar;
+  b.p[BUF_PART] = h->adj_part;
   return h->adj.run(b, h->ctx->stream, DMRG_FP64);
 }
 
 }  // extern "C"
+
+extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps) {
+  if (!h || !psi || !y || reps < 1 || psi == y) return fail(DMRG_EINVAL, "heff_autotune: bad arguments");
+  hipStream_t s = h->ctx->stream;
+  const Program& P = h->fwd;
+  // problems of the current plan grouped by (phase, M bucket, N bucket)
+  std::map<int, std::vector<int32_t>> groups;
+  for (size_t pi = 0; pi < P.probs.size(); ++pi) {
+    const Prob& p = P.probs[pi];
+    const int key = (p.pad0 * TUNE_BUCKETS + size_bucket(p.M)) * TUNE_BUCKETS + size_bucket(p.N);
+    groups[key].push_back((int32_t)pi);
+  }
+  size_t max_tiles = 1;
+  for (auto& kv : groups) {
+    size_t n = 0;
+    for (int32_t pi : kv.second) n += (size_t)((P.probs[pi].M + 31) / 32) * ((P.probs[pi].N + 31) / 32);
+    max_tiles = std::max(max_tiles, n);
+  }
+  Tile* dt = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (dt) (void)hipFree(dt);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&dt, max_tiles * sizeof(Tile)) != hipSuccess) {
+    dt = nullptr;
+    return fail(DMRG_ENOMEM, "heff_autotune: device allocation failed");
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(DMRG_EHIP, "heff_autotune: hipEventCreate failed");
+  }
+  const Bases b = fwd_bases(h, psi, y);
+  TuneTable table;
+  for (auto& kv : groups) {
+    float best = 0.f;
+    int best_cfg = -1;
+    for (int cfg = 0; cfg < CFG_F64_COUNT; ++cfg) {
+      const int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
+      std::vector<Tile> tl;
+      for (int32_t pi : kv.second) {
+        const Prob& p = P.probs[pi];
+        for (int i = 0; i < (p.M + bm - 1) / bm; ++i)
+          for (int j = 0; j < (p.N + bn - 1) / bn; ++j) tl.push_back(Tile{pi, (int16_t)i, (int16_t)j});
+      }
+      Launch l{cfg, h->prec, 0, (int64_t)tl.size()};
+      float ms = 0.f;
+      dmrg_status st = DMRG_OK;
+      if (hipMemcpyAsync(dt, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = fail(DMRG_EHIP, "heff_autotune: copy failed");
+      if (st == DMRG_OK) st = launch_gemm(l, b, P.d_probs, P.d_segs, dt, s);  // warm-up
+      if (st == DMRG_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(DMRG_EHIP, "event");
+      for (int r = 0; r < reps && st == DMRG_OK; ++r) st = launch_gemm(l, b, P.d_probs, P.d_segs, dt, s);
+      if (st == DMRG_OK && hipEventRecord(e1, s) != hipSuccess) st = fail(DMRG_EHIP, "event");
+      if (st == DMRG_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(DMRG_EHIP, "event sync");
+      if (st == DMRG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = fail(DMRG_EHIP, "elapsed");
+      if (st != DMRG_OK) {
+        cleanup();
+        return st;
+      }
+      if (best_cfg < 0 || ms < best) {
+        best = ms;
+        best_cfg = cfg;
+      }
+    }
+    const int key = kv.first;
+    table.cfg[key / (TUNE_BUCKETS * TUNE_BUCKETS)][(key / TUNE_BUCKETS) % TUNE_BUCKETS][key % TUNE_BUCKETS] =
+        (int8_t)best_cfg;
+  }
+  cleanup();
+  // rebuild the forward program with the chosen shapes
+  h->tune = table;
+  Program old = std::move(h->fwd);
+  h->fwd = Program();
+  dmrg_status st = build_forward(h, -1);
+  if (st == DMRG_OK && h->fwd.part_elems > old.part_elems) st = fail(DMRG_EQN, "autotune: partials grew");
+  if (st == DMRG_OK) {
+    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0,
+                              std::max(h->fwd.part_elems, old.part_elems)};
+    st = h->fwd.validate(len);
+  }
+  if (st == DMRG_OK) st = h->fwd.upload();
+  if (st != DMRG_OK) {
+    h->fwd.release();
+    h->fwd = std::move(old);
+    return st;
+  }
+  old.release();
+  free_graph(h);
+  return DMRG_OK;
+}

@@ -141,6 +141,14 @@ class Heff:
         check(lib().dmrg_heff_apply(self.h, _ptr(psi), _ptr(y)))
         return y
 
+    def autotune(self, psi, scratch=None, reps=3):
+        """Pick the fastest tile shape per problem class on this plan's own
+        problems (timed on the device) and rebuild the plan with it."""
+        self._vec(psi, "psi")
+        y = torch.empty_like(psi) if scratch is None else self._vec(scratch, "scratch")
+        self.ctx.sync_stream()
+        check(lib().dmrg_heff_autotune(self.h, _ptr(psi), _ptr(y), int(reps)))
+
     def launches(self):
         """(kernel ids, algorithmic FLOPs) of the matvec's launches."""
         n = c_int64()
@@ -214,12 +222,13 @@ class HeffApply(torch.autograd.Function):
 
 
 def davidson(heff: Heff, psi, tol=1e-8, max_iter=200, max_subspace=24, restart_keep=2, use_graph=False,
-             fp64_tail=0):
-    """Lowest eigenpair of H_eff on the device; psi (start vector) is
-    overwritten by the Ritz vector.  Returns a dict of the solver result."""
+             fp64_tail=0, start_from_diag=False):
+    """Lowest eigenpair of H_eff on the device; psi (start vector, ignored
+    with start_from_diag) is overwritten by the Ritz vector.  Returns a dict
+    of the solver result."""
     heff._vec(psi, "psi")
     opts = DavOpts(int(max_iter), int(max_subspace), int(restart_keep), 1 if use_graph else 0, float(tol),
-                   int(fp64_tail), 0)
+                   int(fp64_tail), 1 if start_from_diag else 0)
     res = DavResult()
     heff.ctx.sync_stream()
     st = lib().dmrg_davidson(heff.h, _ptr(psi), byref(opts), byref(res))

@@ -57,16 +57,18 @@ def test_davidson_l24_reduced_vs_oracle(ctx):
     from paper_2407_07411_amd.heff import davidson
     from tests.test_gpu_heff import _l24
     prob = _l24(1)
-    ref = oracle_davidson(lambda v: heff_apply(prob, v), heff_diag(prob), x0=prob.psi.numpy(), tol=1e-8)
+    # start from the unit vector at the lowest diagonal element (a random
+    # start converges far more slowly on these synthetic spectra)
+    ref = oracle_davidson(lambda v: heff_apply(prob, v), heff_diag(prob), x0=None, tol=1e-8)
     h = gpu_heff(ctx, prob)
     psi = prob.psi.to("cuda").clone()
-    res = davidson(h, psi, tol=1e-8)
+    res = davidson(h, psi, tol=1e-8, start_from_diag=True)
     print(res, ref["energy"], ref["iters"], flush=True)
     assert res["converged"] and ref["converged"]
     assert abs(res["energy"] - ref["energy"]) < 1e-8
 
 
-def test_davidson_config1_centre_is_fci(ctx):
+def test_davidson_l8_centre_is_fci(ctx):
     from oracle.fci import fci_energy
     from oracle.physical import physical_problem
     from paper_2407_07411_amd.heff import davidson

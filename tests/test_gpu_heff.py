@@ -151,3 +151,40 @@ def test_physical_centre_matvec(ctx):
     g = gpu_heff(ctx, prob)
     y = g.apply(torch.from_numpy(x).cuda()).cpu().numpy()
     assert rel(y, heff_apply(prob, x)) <= TOL
+
+
+def test_autotune_keeps_results(ctx, l24):
+    """Tile shapes change only the tiling, not any element's summation
+    order (same K sequence, same 4-deep MFMA steps), so the autotuned plan
+    reproduces the default plan bit for bit."""
+    h = gpu_heff(ctx, l24)
+    x = l24.psi.to("cuda")
+    y0 = h.apply(x).clone()
+    h.autotune(x, reps=2)
+    y1 = h.apply(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert rel(y1.cpu().numpy(), heff_apply(l24)) <= TOL
+
+
+@pytest.mark.parametrize("kchunk", ["64", "700"])
+def test_split_k_sums(ctx, l24, kchunk, monkeypatch):
+    """Output sums cut into K parts (partials reduced in part order) agree
+    with the oracle, and repeat bit for bit."""
+    print("case kchunk", kchunk, flush=True)
+    monkeypatch.setenv("DMRG_HEFF_KCHUNK", kchunk)
+    monkeypatch.setenv("DMRG_HEFF_WORKSPACE_MB", "8")
+    h = gpu_heff(ctx, l24)
+    x = l24.psi.to("cuda")
+    y0 = h.apply(x).clone()
+    y1 = h.apply(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert rel(y0.cpu().numpy(), heff_apply(l24)) <= TOL
+    # adjoint programs cut their long sums the same way
+    rng = np.random.default_rng(4)
+    yb = rng.standard_normal(h.size)
+    gp = torch.zeros_like(x)
+    h.adjoint(x, torch.from_numpy(yb).cuda(), gp, None, None)
+    pb, _, _ = heff_adjoint(l24, l24.psi.numpy(), yb)
+    assert rel(gp.cpu().numpy(), pb) <= TOL

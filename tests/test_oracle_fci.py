@@ -16,20 +16,20 @@ from synth.integrals import hubbard_dimer, integrals
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def l8():
     h, V = integrals(8, 1001)
     H, idx = fci_hamiltonian(h, V, 4, 4)
     return h, V, H, idx
 
 
-def test_config1_dimension(cfg1):
-    _, _, H, idx = cfg1
+def test_l8_dimension(l8):
+    _, _, H, idx = l8
     # C(8,4)^2 determinants for 4 alpha + 4 beta electrons in 8 orbitals
     assert H.shape == (4900, 4900) and len(idx) == 4900
 
 
-def test_config1_symmetric(cfg1):
-    _, _, H, _ = cfg1
+def test_l8_symmetric(l8):
+    _, _, H, _ = l8
     assert abs(H - H.T).max() <= 1e-13 * abs(H).max()
 
 
@@ -60,8 +60,8 @@ def test_hubbard_dimer(t, U):
     assert abs(e - (U - np.sqrt(U * U + 16 * t * t)) / 2) < 1e-13
 
 
-def test_hartree_fock_diagonal(cfg1):
-    h, V, H, idx = cfg1
+def test_hartree_fock_diagonal(l8):
+    h, V, H, idx = l8
     # determinant with orbitals 0..3 doubly occupied: modes 0..7 set
     x_hf = (1 << 8) - 1
     k = int(np.nonzero(idx == x_hf)[0][0])

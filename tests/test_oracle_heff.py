@@ -4,7 +4,7 @@
   assembled dense sum of Kronecker products over the full enlarged spaces,
   restricted to the wavefunction's blocks;
 * physics: with operator pairs of the real Hamiltonian, the operator sum is
-  P^T H_FCI P, and at the config-1 centre (full Fock blocks) its ground
+  P^T H_FCI P, and at the L=8 centre bond (full Fock blocks) its ground
   state is the FCI energy;
 * invariants: Hermiticity, linearity, the diagonal, and the reduction of a
   single dq = 0 term to A Psi B^T.
@@ -133,19 +133,19 @@ def test_physical_pairs_are_projected_fci(L, m, na, nb, keep):
     prob = physical_problem(h, V, m, na, nb, isoL, isoR)
     H, idx = fci_hamiltonian(h, V, na, nb)
     P = embedding(prob, idx)
-    assert np.abs(P.T @ P - np.eye(P.shape[1])).max() < 1e-13          # C4 (a)
+    assert np.abs(P.T @ P - np.eye(P.shape[1])).max() < 1e-13        
     He = heff_dense(prob)
     Hp = P.T @ (H @ P)
-    assert np.abs(He - Hp).max() < 1e-12 * max(1.0, np.abs(Hp).max())  # C5 (e)
-    assert np.abs(He - He.T).max() < 1e-12                                # C4 (b)
+    assert np.abs(He - Hp).max() < 1e-12 * max(1.0, np.abs(Hp).max())
+    assert np.abs(He - He.T).max() < 1e-12                              
     e_fci = fci_energy(h, V, na, nb, dense=True)
-    assert np.linalg.eigvalsh(He)[0] >= e_fci - 1e-10                     # C4 (d)
+    assert np.linalg.eigvalsh(He)[0] >= e_fci - 1e-10                   
 
 
-def test_config1_centre_recovers_fci():
-    """Config-1 centre two-site step: blocks of 4 orbitals hold every Fock
+def test_l8_centre_recovers_fci():
+    """L=8 centre two-site step: blocks of 4 orbitals hold every Fock
     state (64 = D states per 3-orbital block, times the 4 site states), so
-    the two-site space is the full 4900-dim FCI space (C4 (c))."""
+    the two-site space is the full 4900-dim FCI space."""
     h, V = integrals(8, 1001)
     prob = physical_problem(h, V, 4, 4, 4)
     lay = layout_of(prob)
@@ -160,7 +160,7 @@ def test_config1_centre_recovers_fci():
     assert abs(res["energy"] - e_fci) < 1e-9
 
 
-def test_config1_ground_state_is_triplet():
+def test_l8_ground_state_is_triplet():
     h, V = integrals(8, 1001)
     assert abs(fci_energy(h, V, 5, 3) - fci_energy(h, V, 4, 4)) < 1e-9
 
