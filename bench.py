@@ -27,7 +27,11 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "gemm_f64_kernel<32,32,16,1,1>", 1: "gemm_f64_kernel<64,64,16,2,2>",
-                2: "gemm_f64_kernel<128,128,16,2,2>"}
+                2: "gemm_f64_kernel<128,128,16,2,2>", 3: "gemm_f64_kernel<128,128,16,4,2>",
+                4: "gemm_f64_kernel<256,128,16,4,2>", 16: "gemm_split_kernel<32,32,1,1>",
+                17: "gemm_split_kernel<64,64,2,2>", 18: "gemm_split_kernel<128,128,2,2>",
+                19: "gemm_split_kernel<128,128,4,2>", 20: "gemm_split_kernel<256,128,4,2>",
+                32: "reduce_kernel"}
 
 
 def parse():
@@ -40,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the Davidson-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile-shape rule")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -61,6 +68,13 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copied 1 GiB (counter calibration)")
     t0 = time.time()
     prob = make_problem(w["L"], w["n_elec"], w["two_sz"], w["D"], w["seed"], device=dev,
                         pool_budget_bytes=int(args.pool_gb * 1e9))
@@ -79,6 +93,10 @@ def main():
             f"({time.time()-t0:.1f} s)")
         x = prob.psi.clone()
         y = torch.empty_like(x)
+        if not args.no_tune:
+            t0 = time.time()
+            h.autotune(x, y, reps=2)
+            log(f"autotuned tile shapes ({time.time()-t0:.1f} s)")
 
         # ---- matvec alone (FP64): warm-up, then HIP events on this stream
         for _ in range(2):
@@ -102,6 +120,10 @@ def main():
             a[0] += f
             a[1] += m
             a[2] += 1
+        for k in sorted(per):
+            f_, m_, n_ = per[k]
+            log(f"  {KERNEL_NAMES.get(k, k)}: {n_} launches, {m_:.1f} ms ({100*m_/float(ms.sum()):.0f}%), "
+                f"{f_/(m_/1e3)/1e12 if m_ > 0 else 0:.1f} TFLOP/s")
         dom = max(per, key=lambda k: per[k][1])
         dflops, dms, dn = per[dom]
         achieved = dflops / (dms / 1e3) / 1e12

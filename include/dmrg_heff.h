@@ -163,8 +163,10 @@ dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int3
 /* Profiling: the matvec is a fixed sequence of grouped-GEMM launches.
  * n_launches (host) receives their number; when kernel / flops are non-null
  * (host arrays of at least that many entries) they receive each launch's
- * kernel id (0: 32x32 tile, 1: 64x64, 2: 128x128; +16 for the split-precision
- * kernels) and its algorithmic FLOPs (2 M N K summed over its problems). */
+ * kernel id (FP64 grouped GEMM tiles 0: 32x32, 1: 64x64, 2: 128x128 with 4
+ * waves, 3: 128x128 with 8 waves, 4: 256x128 with 8 waves; +16 for the split
+ * precision kernels; 32: the ordered reduction of cut K sums) and its
+ * algorithmic FLOPs (2 M N K summed over its problems, 0 for reductions). */
 dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops);
 /* y = H_eff psi as dmrg_heff_apply (eager), bracketing every launch with HIP
  * events on the context stream; ms (host float[n_launches]) receives each
@@ -191,6 +193,9 @@ typedef struct {
   int32_t matvecs;
   int32_t converged;
   int32_t tail_iters;    /* iterations spent in the FP64 tail                 */
+  double split_residual; /* residual where the split-precision phase ended   */
+  int32_t split_iters;   /* iterations of the split-precision phase          */
+  int32_t reserved;
 } dmrg_dav_result;
 
 /* Davidson (E. R. Davidson 1975) for the lowest eigenpair of H_eff with the

@@ -711,9 +711,18 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmr
   std::vector<double> hist;
   dmrg_dav_result r1{};
   dmrg_status st = solve(h, psi_inout, opts, &r1, [&](const dmrg_dav_result& r) {
+    // Leave once the residual is within reach of the split matvec's own error
+    // (relative ~1e-7, so a residual of ~5e-6 |theta|), or once it is small
+    // and has stopped improving (best value not 10% better over 8 steps).
     hist.push_back(r.residual);
+    const double scale = std::max(1.0, std::fabs(r.energy));
+    if (r.residual <= 5e-6 * scale) return true;
     const size_t n = hist.size();
-    return n >= 4 && hist[n - 1] > 0.5 * hist[n - 4];
+    if (n < 9 || r.residual > 1e-3 * scale) return false;
+    double best_before = hist[0], best_recent = hist[n - 8];
+    for (size_t i = 0; i + 8 < n; ++i) best_before = std::min(best_before, hist[i]);
+    for (size_t i = n - 8; i < n; ++i) best_recent = std::min(best_recent, hist[i]);
+    return best_recent > 0.9 * best_before;
   });
   if (st != DMRG_OK && st != DMRG_ENOCONV) return st;
   dmrg_dav_opts o2 = *opts;
@@ -726,5 +735,7 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmr
   res->iters = r1.iters + r2.iters;
   res->matvecs = r1.matvecs + r2.matvecs;
   res->tail_iters = r2.iters;
+  res->split_iters = r1.iters;
+  res->split_residual = r1.residual;
   return st;
 }

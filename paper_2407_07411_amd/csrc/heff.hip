@@ -139,7 +139,7 @@ int64_t kchunk_from_env() {
 
 // Tile shape for one output matrix.
 int choose_cfg(int M, int N) {
-  if (M >= 96 && N >= 96) return CFG_F64_128;
+  if (M >= 96 && N >= 96) return CFG_F64_128W8;
   if (M >= 40 && N >= 40) return CFG_F64_64;
   return CFG_F64_32;
 }

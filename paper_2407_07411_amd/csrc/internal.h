@@ -71,10 +71,12 @@ static_assert(sizeof(Tile) == 8, "Tile layout");
 
 // Tile shapes the kernels are instantiated for.
 enum TileCfg : int32_t {
-  CFG_F64_32 = 0,   // 32x32 tile, 1 wave (2x2 MFMA blocks)
-  CFG_F64_64 = 1,   // 64x64 tile, 4 waves (2x2 each)
-  CFG_F64_128 = 2,  // 128x128 tile, 4 waves (4x4 each)
-  CFG_F64_COUNT = 3
+  CFG_F64_32 = 0,      // 32x32 tile, 1 wave
+  CFG_F64_64 = 1,      // 64x64 tile, 4 waves
+  CFG_F64_128 = 2,     // 128x128 tile, 4 waves
+  CFG_F64_128W8 = 3,   // 128x128 tile, 8 waves (two per SIMD)
+  CFG_F64_256x128 = 4, // 256x128 tile, 8 waves
+  CFG_F64_COUNT = 5
 };
 int cfg_bm(int cfg);
 int cfg_bn(int cfg);

@@ -30,6 +30,8 @@ int cfg_from_env() {
   if (v == 32) return CFG_F64_32;
   if (v == 64) return CFG_F64_64;
   if (v == 128) return CFG_F64_128;
+  if (v == 1288) return CFG_F64_128W8;
+  if (v == 256) return CFG_F64_256x128;
   return -1;
 }
 
@@ -649,7 +651,7 @@ dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kern
   *n_launches = (int64_t)P.launches.size();
   for (size_t i = 0; i < P.launches.size(); ++i) {
     const Launch& l = P.launches[i];
-    if (kernel) kernel[i] = l.cfg == CFG_REDUCE ? 3 : l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : 0);
+    if (kernel) kernel[i] = l.cfg == CFG_REDUCE ? 32 : l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : 0);
     if (flops && l.cfg == CFG_REDUCE) {
       flops[i] = 0.0;
     } else if (flops) {
@@ -792,6 +794,8 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
     float best = 0.f;
     int best_cfg = -1;
     for (int cfg = 0; cfg < CFG_F64_COUNT; ++cfg) {
+      // the split kernel's 256x128 shape spills registers: not a candidate
+      if (h->prec == DMRG_SPLIT_BF16X3 && cfg == CFG_F64_256x128) continue;
       const int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
       std::vector<Tile> tl;
       for (int32_t pi : kv.second) {

@@ -235,7 +235,8 @@ def davidson(heff: Heff, psi, tol=1e-8, max_iter=200, max_subspace=24, restart_k
     if st not in (0, -5):
         check(st)
     return dict(energy=res.energy, residual=res.residual, iters=res.iters, matvecs=res.matvecs,
-                converged=bool(res.converged), tail_iters=res.tail_iters, status=st)
+                converged=bool(res.converged), tail_iters=res.tail_iters, split_iters=res.split_iters,
+                split_residual=res.split_residual, status=st)
 
 
 def svd_truncate(ctx: Context, Lq, Ld, Rq, Rd, Q, psi, max_keep, cutoff=0.0):
