@@ -237,6 +237,48 @@ dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, co
                               int64_t* kept_dim, double* U, int64_t u_cap, double* S,
                               int64_t s_cap, double* Vt, int64_t vt_cap, double* trunc_err);
 
+/* ---- operator blocks and the two-site sweep -------------------------------- */
+/* The ab initio Hamiltonian H = sum h_pq a+_ps a_qs + 1/2 sum V_pqrs
+ * a+_ps a+_rt a_st a_qs on an orbital chain, with the operator blocks of a
+ * two-site DMRG sweep (the paper's MPS optimisation, Numerical procedure
+ * section).  h: host double[L*L]; V: host double[L^4], V_pqrs = (pq|rs) at
+ * ((p*L+q)*L+r)*L+s; n_elec electrons with 2Sz = two_sz; at most D states per
+ * block.  The right blocks are first built from a random isometry per sector
+ * (seeded).  ctx may be NULL when only dmrg_chain_export is called.  Blocks keep H, all one- and two-operator products on their
+ * orbitals and the complementary sums for operators outside them, in their
+ * renormalised bases. */
+typedef struct dmrg_chain_s* dmrg_chain_t;
+dmrg_status dmrg_chain_create(dmrg_ctx_t ctx, int32_t L, const double* h, const double* V,
+                              int32_t n_elec, int32_t two_sz, int64_t D, uint64_t seed,
+                              dmrg_chain_t* out);
+void dmrg_chain_destroy(dmrg_chain_t c);
+/* One two-site update at orbitals (l, l+1): grow the left block [0,l) by l
+ * and the right block [l+2,L) by l+1, build the H_eff operator pairs, solve
+ * for the lowest state with Davidson (seeded random start, opts as for
+ * dmrg_davidson), truncate with dmrg_svd_truncate to D states and keep the
+ * renormalised enlarged block of the sweep direction (dir = +1: left block
+ * [0,l+1); dir = -1: right block [l+1,L)).  A left-to-right sweep runs
+ * l = 0..L-2 with dir = +1, a right-to-left sweep l = L-2..0 with dir = -1.
+ * energy, trunc_err: host.  Synchronises. */
+dmrg_status dmrg_chain_step(dmrg_chain_t c, int32_t l, int32_t dir, const dmrg_dav_opts* opts,
+                            double* energy, double* trunc_err, dmrg_dav_result* res);
+/* Host-only: (re)build the left blocks [0,1) .. [0,l) by growth without
+ * truncation (every state compatible with the total charge is kept), e.g. to
+ * start a sweep from exact small blocks or to inspect dmrg_chain_export. */
+dmrg_status dmrg_chain_grow_left(dmrg_chain_t c, int32_t l);
+/* The two-site problem dmrg_chain_step would solve at (l, l+1), as host
+ * arrays (host-only, needs no device: ctx may be NULL at dmrg_chain_create if
+ * only this call is used).  Call once with null arrays to get n_left,
+ * n_right, n_terms and the pool lengths, then with arrays of those sizes:
+ * lqn[n_left][2], ldim[n_left], rqn[n_right][2], rdim[n_right],
+ * term_info[n_terms][4] = (dq N, dq 2Sz, odd, one_sided), left_off[n_terms]
+ * [n_left], right_off[n_terms][n_right] (layout of dmrg_term, -1 absent),
+ * lpool, rpool.  Every term has coefficient 1 and no hermitian partner. */
+dmrg_status dmrg_chain_export(dmrg_chain_t c, int32_t l, int32_t* n_left, int32_t* n_right,
+                              int64_t* n_terms, int64_t* lpool_len, int64_t* rpool_len, int32_t* lqn,
+                              int64_t* ldim, int32_t* rqn, int64_t* rdim, int32_t* term_info,
+                              int64_t* left_off, int64_t* right_off, double* lpool, double* rpool);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,15 @@ SIGNATURES = {
     "dmrg_davidson_vector": (c_int, [c_void_p, c_void_p]),
     "dmrg_davidson_destroy": (None, [c_void_p]),
     "dmrg_davidson": (c_int, [c_void_p, c_void_p, POINTER(DavOpts), POINTER(DavResult)]),
+    "dmrg_chain_create": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int32, c_int64,
+                                  ctypes.c_uint64, POINTER(c_void_p)]),
+    "dmrg_chain_destroy": (None, [c_void_p]),
+    "dmrg_chain_step": (c_int, [c_void_p, c_int32, c_int32, POINTER(DavOpts), POINTER(c_double),
+                                POINTER(c_double), POINTER(DavResult)]),
+    "dmrg_chain_grow_left": (c_int, [c_void_p, c_int32]),
+    "dmrg_chain_export": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64),
+                                  POINTER(c_int64), POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_svd_truncate": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_void_p, c_int64, c_double,
                                   POINTER(c_int64), c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                   POINTER(c_double)]),
