@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the Davidson-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile-shape rule")
+    ap.add_argument("--tune", action="store_true", help="run the tile-shape autotuner before timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     return ap.parse_args()
@@ -93,7 +93,7 @@ def main():
             f"({time.time()-t0:.1f} s)")
         x = prob.psi.clone()
         y = torch.empty_like(x)
-        if not args.no_tune:
+        if args.tune:
             t0 = time.time()
             h.autotune(x, y, reps=2)
             log(f"autotuned tile shapes ({time.time()-t0:.1f} s)")
