@@ -34,6 +34,45 @@ KERNEL_NAMES = {0: "gemm_f64_kernel<32,32,16,1,1>", 1: "gemm_f64_kernel<64,64,16
                 32: "reduce_kernel"}
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_SOURCES = ("paper_2407_07411_amd/csrc", "include", "synth")
+
+
+def sources_digest():
+    """SHA-256 over the kernel, plan and input-generator sources: a stored HBM
+    byte count is reported only while these are unchanged."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for d in TRAFFIC_SOURCES:
+        for name in sorted(os.listdir(os.path.join(ROOT, d))):
+            if name.endswith((".hip", ".h", ".py")):
+                hsh.update(name.encode())
+                with open(os.path.join(ROOT, d, name), "rb") as f:
+                    hsh.update(f.read())
+    return hsh.hexdigest()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
+    None when there is none or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("sources_sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 2 and cells[0] == f"`{kernel}`":
+                try:
+                    val = float(cells[-1])
+                except ValueError:
+                    pass
+    return val if digest == sources_digest() else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,9 +166,12 @@ def main():
         dom = max(per, key=lambda k: per[k][1])
         dflops, dms, dn = per[dom]
         achieved = dflops / (dms / 1e3) / 1e12
+        dname = KERNEL_NAMES.get(dom, str(dom))
+        traffic = profiled_traffic(dname, args.workload) if args.pool_gb == 150.0 else None
         roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                        frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
-                        kernel=KERNEL_NAMES.get(dom, str(dom)), launches=dn,
+                        frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=traffic,
+                        traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                        kernel=dname, launches=dn,
                         avg_launch_ms=round(dms / dn, 4), flops_per_launch=dflops / dn,
                         share_of_matvec=round(dms / float(ms.sum()), 3))
         log(f"dominant kernel {roofline['kernel']}: {achieved:.2f} TFLOP/s over {dn} launches")

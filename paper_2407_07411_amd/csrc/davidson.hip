@@ -354,6 +354,12 @@ __global__ void copy_kernel(const double* __restrict__ a, int64_t n, double* __r
     b[e] = a[e];
 }
 
+// b -= a
+__global__ void diff_kernel(const double* __restrict__ a, int64_t n, double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] -= a[i];
+}
+
 __global__ void zero_kernel(double* __restrict__ b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     b[e] = 0.0;
@@ -697,6 +703,42 @@ dmrg_status solve(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts, d
   return st;
 }
 
+
+// The split matvec's own error on a generic vector, ||(H_split - H) u|| for
+// u = psi / ||psi||: the level below which split-precision residuals stop
+// meaning anything.  Costs one FP64 and one split matvec.
+dmrg_status split_floor(dmrg_heff_t h, const double* psi, double* delta) {
+  const int64_t n = dmrg_heff_size(h);
+  if (n <= 0) return fail(DMRG_EINVAL, "davidson: empty wavefunction");
+  dmrg_status st = DMRG_OK;
+  hipStream_t s = h->ctx->stream;
+  double* mem = nullptr;
+  const int64_t len = 2 * n + (int64_t)RED_BLOCKS * KMAX + 2;
+  if (hipMalloc(&mem, len * sizeof(double)) != hipSuccess) return fail(DMRG_ENOMEM, "davidson: allocation failed");
+  double *y64 = mem, *ys = mem + n, *partial = mem + 2 * n, *out = partial + (int64_t)RED_BLOCKS * KMAX;
+  const int keep = h->prec;
+  h->prec = DMRG_FP64;
+  st = heff_apply_eager(h, psi, y64);
+  h->prec = DMRG_SPLIT_BF16X3;
+  if (st == DMRG_OK) st = heff_apply_eager(h, psi, ys);
+  h->prec = keep;
+  double host[2] = {0.0, 0.0};
+  if (st == DMRG_OK) {
+    diff_kernel<<<grid_for(n), 256, 0, s>>>(y64, n, ys);
+    scalar_dot_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(ys, ys, n, partial);
+    finish_scalar_kernel<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, out);
+    scalar_dot_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(psi, psi, n, partial);
+    finish_scalar_kernel<<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, out + 1);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = fail(DMRG_EHIP, "davidson: split error estimate failed");
+  }
+  (void)hipFree(mem);
+  if (st == DMRG_OK) *delta = host[1] > 0.0 ? std::sqrt(host[0] / host[1]) : 0.0;
+  return st;
+}
+
 }  // namespace
 
 extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts,
@@ -704,21 +746,22 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmr
   if (!h || !psi_inout || !opts || !res) return fail(DMRG_EINVAL, "davidson: bad arguments");
   if (h->prec != DMRG_SPLIT_BF16X3 || opts->fp64_tail <= 0)
     return solve(h, psi_inout, opts, res, [](const dmrg_dav_result&) { return false; });
-  // Split-precision phase: iterate while the residual keeps falling (it
-  // levels off near the matvec's own error), then an FP64 tail restarted from
-  // that Ritz vector brings the residual, the energy and the vector to the
-  // FP64 tolerance.
+  // Split-precision phase until the residual reaches a few times the split
+  // matvec's own error (or the tolerance, or stops falling near that level),
+  // then an FP64 tail from that Ritz vector brings the residual, the energy
+  // and the vector to the FP64 tolerance.
+  double delta = 0.0;
+  dmrg_status st = split_floor(h, psi_inout, &delta);
+  if (st != DMRG_OK) return st;
+  const double exit_at = std::max(opts->tol, 4.0 * delta);
   std::vector<double> hist;
   dmrg_dav_result r1{};
-  dmrg_status st = solve(h, psi_inout, opts, &r1, [&](const dmrg_dav_result& r) {
-    // Leave once the residual is within reach of the split matvec's own error
-    // (relative ~1e-7, so a residual of ~5e-6 |theta|), or once it is small
-    // and has stopped improving (best value not 10% better over 8 steps).
+  st = solve(h, psi_inout, opts, &r1, [&](const dmrg_dav_result& r) {
     hist.push_back(r.residual);
-    const double scale = std::max(1.0, std::fabs(r.energy));
-    if (r.residual <= 5e-6 * scale) return true;
+    if (r.residual <= exit_at) return true;
+    // safety: near the floor and no 10% gain over 8 steps
     const size_t n = hist.size();
-    if (n < 9 || r.residual > 1e-3 * scale) return false;
+    if (n < 9 || r.residual > 100.0 * exit_at) return false;
     double best_before = hist[0], best_recent = hist[n - 8];
     for (size_t i = 0; i + 8 < n; ++i) best_before = std::min(best_before, hist[i]);
     for (size_t i = n - 8; i < n; ++i) best_recent = std::min(best_recent, hist[i]);
@@ -727,13 +770,14 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmr
   if (st != DMRG_OK && st != DMRG_ENOCONV) return st;
   dmrg_dav_opts o2 = *opts;
   o2.max_iter = opts->fp64_tail;
+  o2.start = 0;  // from the split phase's Ritz vector
   h->prec = DMRG_FP64;
   dmrg_dav_result r2{};
   st = solve(h, psi_inout, &o2, &r2, [](const dmrg_dav_result&) { return false; });
   h->prec = DMRG_SPLIT_BF16X3;
   *res = r2;
   res->iters = r1.iters + r2.iters;
-  res->matvecs = r1.matvecs + r2.matvecs;
+  res->matvecs = r1.matvecs + r2.matvecs + 2;
   res->tail_iters = r2.iters;
   res->split_iters = r1.iters;
   res->split_residual = r1.residual;

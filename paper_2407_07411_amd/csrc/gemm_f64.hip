@@ -117,10 +117,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
   const Tile t = tiles[lt];
   const Prob p = probs[t.prob];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WGN, wn = wave % WGN;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // Output sub-tile of this wave, rotated by block so that the waves an edge
+  // tile leaves idle fall on different SIMDs from block to block.
+  constexpr int NW = WGM * WGN;
+  const int role = (wave + 2 * (int)(blockIdx.x & 3)) % NW;
+  const int wm = role / WGN, wn = role % WGN;
   const int m0 = t.tm * BM, n0 = t.tn * BN;
   const int fr = lane & 15, fk = lane >> 4;
+  const bool active = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
 
   d4 acc[FM][FN];
 #pragma unroll
@@ -150,18 +155,22 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
       if (more)
         regs.load(g2, bases.p[g2.xbuf] + g2.xoff, bases.p[g2.zbuf] + g2.zoff, k2, m0, n0, p.M, p.N,
                   tid);
+      // edge tiles: a wave whose output rows or columns all lie outside the
+      // problem issues no LDS reads or MFMAs
+      if (active) {
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double a[FM], b[FN];
+        for (int kk = 0; kk < BK; kk += 4) {
+          double a[FM], b[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kk + fk][wm * WM + i * 16 + fr];
+          for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kk + fk][wm * WM + i * 16 + fr];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) b[j] = Zs[buf][kk + fk][wn * WN + j * 16 + fr];
+          for (int j = 0; j < FN; ++j) b[j] = Zs[buf][kk + fk][wn * WN + j * 16 + fr];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
       }
       if (!more) break;
       // the other buffer was last read before the previous barrier
@@ -226,24 +235,39 @@ dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, cons
 
 // ---------------------------------------------------------------------------
 // Diagonal of H_eff: element (i, j) of block B is the sum over the dq = 0
-// pairs reaching B of alpha * Adiag[i] * Bdiag[j]; blocks are independent, so
-// one thread owns one element and sums its pairs in list order.
-__global__ void diag_kernel(const DiagBlock* __restrict__ blocks, int nblocks,
-                            const DiagItem* __restrict__ items, const double* __restrict__ lpool,
-                            const double* __restrict__ rpool, double* __restrict__ out) {
+// pairs reaching B of alpha * Adiag[i] * Bdiag[j], summed in list order.
+// A workgroup owns 64 x 64 element tiles of one block (thread: one column,
+// 16 rows), so each strided diagonal entry it reads serves 64 elements.
+constexpr int DIAG_T = 64;
+__global__ __launch_bounds__(256) void diag_kernel(const DiagBlock* __restrict__ blocks, int nblocks,
+                                                   const DiagItem* __restrict__ items,
+                                                   const double* __restrict__ lpool,
+                                                   const double* __restrict__ rpool,
+                                                   double* __restrict__ out) {
+  constexpr int RPT = DIAG_T / 4;  // rows per thread
   const DiagBlock bk = blocks[blockIdx.y];
-  const int64_t n = (int64_t)bk.dl * bk.dr;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / bk.dr), j = (int)(e % bk.dr);
-    double acc = 0.0;
+  const int tx = threadIdx.x % DIAG_T, ty = threadIdx.x / DIAG_T;
+  const int tr = (bk.dl + DIAG_T - 1) / DIAG_T, tc = (bk.dr + DIAG_T - 1) / DIAG_T;
+  for (int tile = blockIdx.x; tile < tr * tc; tile += gridDim.x) {
+    const int i0 = (tile / tc) * DIAG_T, j = (tile % tc) * DIAG_T + tx;
+    double acc[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
     for (int it = bk.item0; it < bk.item0 + bk.nitem; ++it) {
       const DiagItem d = items[it];
-      const double a = d.aoff >= 0 ? lpool[d.aoff + (int64_t)i * (d.da + 1)] : 1.0;
-      const double bb = d.boff >= 0 ? rpool[d.boff + (int64_t)j * (d.db + 1)] : 1.0;
-      acc += d.alpha * a * bb;
+      const double bb = j < bk.dr ? (d.boff >= 0 ? rpool[d.boff + (int64_t)j * (d.db + 1)] : 1.0) : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = i0 + ty + 4 * r;
+        const double a = i < bk.dl ? (d.aoff >= 0 ? lpool[d.aoff + (int64_t)i * (d.da + 1)] : 1.0) : 0.0;
+        acc[r] += d.alpha * a * bb;
+      }
     }
-    out[bk.off + e] = acc;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = i0 + ty + 4 * r;
+      if (i < bk.dl && j < bk.dr) out[bk.off + (int64_t)i * bk.dr + j] = acc[r];
+    }
   }
 }
 
@@ -251,8 +275,8 @@ dmrg_status launch_diag(const DiagBlock* blocks, int nblocks, const DiagItem* it
                         const double* lpool, const double* rpool, double* out, int64_t max_elems,
                         hipStream_t s) {
   if (nblocks <= 0) return DMRG_OK;
-  int64_t gx = (max_elems + 255) / 256;
-  if (gx > 64) gx = 64;
+  int64_t gx = (max_elems + DIAG_T * DIAG_T - 1) / (DIAG_T * DIAG_T);
+  if (gx > 256) gx = 256;
   if (gx < 1) gx = 1;
   diag_kernel<<<dim3((unsigned)gx, (unsigned)nblocks), 256, 0, s>>>(blocks, nblocks, items, lpool,
                                                                      rpool, out);

@@ -7,12 +7,22 @@
 // differences are exact in FP32, so a = a0 + a1 + a2 + O(2^-24 |a|).  The
 // product of two split values keeps the six slice products with i + j <= 2
 // (the dropped ones are O(2^-24) relative).  Slice products are exact in FP32;
-// the matrix cores sum them in FP32, and every SPLIT_FLUSH K tiles the FP32
-// partial is added into an FP64 accumulator, which bounds FP32 rounding to
-// SPLIT_FLUSH * 32 K values.  Global loads of the next K tile are issued into
-// registers before the matrix-core work on the current one.  The
-// problem/segment/tile tables and the output-stationary ordering are those of
-// the FP64 kernel, so results are deterministic.
+// the matrix cores sum them in FP32, and at the end of every segment and every
+// SPLIT_FLUSH K tiles the FP32 partial, times the segment's alpha, is added
+// into an FP64 accumulator, which bounds FP32 rounding to SPLIT_FLUSH * 32 K
+// values.  The problem/segment/tile tables and the output-stationary ordering
+// are those of the FP64 kernel, so results are deterministic.
+//
+// Staging: a thread owns groups of 8 K values of one operand row (one row of X
+// or one column of Z).  Group kg of a row holds k = k0 + kg + 4e, e = 0..7, at
+// LDS positions 8kg + e; X and Z use the same K permutation, so the products
+// are unchanged.  Where the operand is contiguous in K, four neighbouring
+// lanes read one 32-byte run per load; where it is contiguous in the row
+// index, neighbouring lanes read neighbouring rows.  The eight values are
+// converted pairwise (v_cvt_pk_bf16_f32) and each slice lands in LDS as one
+// 16-byte store.  LDS is double-buffered where it fits: the split and store of
+// the next K tile run while the matrix cores work on the current one, and one
+// barrier separates K tiles.
 //
 // Matrix core: v_mfma_f32_32x32x16_bf16.  Lanes: A[i][k] holds i = l%32,
 // k = 8(l/32) + e; B[k][j] holds j = l%32, k = 8(l/32) + e (e = 0..7); the 16
@@ -22,10 +32,15 @@
 namespace dmrg {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 
 constexpr int SPLIT_BK = 32;
-constexpr int SPLIT_FLUSH = 4;  // K tiles per FP32 partial
+constexpr int SPLIT_KG = SPLIT_BK / 8;  // 8-value groups per row and K tile
+constexpr int SPLIT_LDK = SPLIT_BK + 8; // LDS row length (bf16), 80 bytes
+constexpr int SPLIT_FLUSH = 4;          // K tiles per FP32 partial
 
 __device__ __forceinline__ int64_t xcd_remap_s(int64_t bid, int64_t n) {
   const int64_t per = n / 8, rem = n % 8;
@@ -33,85 +48,122 @@ __device__ __forceinline__ int64_t xcd_remap_s(int64_t bid, int64_t n) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-__device__ __forceinline__ void split3(double a, __bf16& h0, __bf16& h1, __bf16& h2) {
-  const float f = (float)a;
-  h0 = (__bf16)f;
-  const float r1 = f - (float)h0;
-  h1 = (__bf16)r1;
-  h2 = (__bf16)(r1 - (float)h1);
+__device__ __forceinline__ uint32_t pk_bits(bf2 h) { return __builtin_bit_cast(uint32_t, h); }
+
+// Split two FP64 values into three packed BF16 pairs.
+__device__ __forceinline__ void split_pair(double a, double b, uint32_t& s0, uint32_t& s1,
+                                           uint32_t& s2) {
+  const f2v f = {(float)a, (float)b};
+  const bf2 h0 = __builtin_convertvector(f, bf2);
+  const f2v r1 = f - __builtin_convertvector(h0, f2v);
+  const bf2 h1 = __builtin_convertvector(r1, bf2);
+  const f2v r2 = r1 - __builtin_convertvector(h1, f2v);
+  const bf2 h2 = __builtin_convertvector(r2, bf2);
+  s0 = pk_bits(h0);
+  s1 = pk_bits(h1);
+  s2 = pk_bits(h2);
 }
 
-template <int BM, int BN, int NT>
-struct SplitRegs {
-  static constexpr int BK = SPLIT_BK;
-  static constexpr int NX = (BM * BK + NT - 1) / NT;
-  static constexpr int NZ = (BN * BK + NT - 1) / NT;
-  double x[NX];
-  double z[NZ];
+// The 8-value groups of one operand (ROWS x BK per K tile) that a thread
+// stages: up to G groups, group r is gi = tid + r * NT < ROWS * SPLIT_KG.
+template <int ROWS, int NT>
+struct Stager {
+  static constexpr int NG = ROWS * SPLIT_KG;
+  static constexpr int G = (NG + NT - 1) / NT;
+  static constexpr bool EXACT = NG % NT == 0;
+  static_assert(EXACT || G == 1, "staging shape");
+  const double* ptr[G];  // address of k = k0 + kg for the group's row
+  int row[G], kg[G];
+  bool rok[G];
+  int64_t estep;         // address step between e and e + 1
+  int64_t tstep;         // address step between K tiles
+  double v[G][8];
 
-  __device__ __forceinline__ void load(const Seg& g, const double* __restrict__ X,
-                                       const double* __restrict__ Z, int k0, int m0, int n0, int M,
-                                       int N, int tid) {
+  // kc: the operand is contiguous in K (element (row, k) at base + row*ld + k);
+  // otherwise it is contiguous in the row index (base + k*ld + row).
+  __device__ __forceinline__ void setup(const double* base, int ld, bool kc, int r0, int nrows,
+                                        int tid) {
+    estep = kc ? (int64_t)SPLIT_KG : (int64_t)SPLIT_KG * ld;
+    tstep = kc ? (int64_t)SPLIT_BK : (int64_t)SPLIT_BK * ld;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      const int i = tid + r * NT;
-      const int mm = g.xt ? i % BM : i / BK, kk = g.xt ? i / BM : i % BK;
-      const int m = m0 + mm, k = k0 + kk;
-      const bool ok = i < BM * BK && m < M && k < g.K;
-      x[r] = ok ? g.alpha * X[g.xt ? (int64_t)k * g.ldx + m : (int64_t)m * g.ldx + k] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < NZ; ++r) {
-      const int i = tid + r * NT;
-      const int nn = g.zt ? i / BK : i % BN, kk = g.zt ? i % BK : i / BN;
-      const int n = n0 + nn, k = k0 + kk;
-      const bool ok = i < BN * BK && n < N && k < g.K;
-      z[r] = ok ? Z[g.zt ? (int64_t)n * g.ldz + k : (int64_t)k * g.ldz + n] : 0.0;
+    for (int r = 0; r < G; ++r) {
+      const int gi = EXACT ? tid + r * NT : min(tid, NG - 1);
+      row[r] = kc ? gi / SPLIT_KG : gi % ROWS;
+      kg[r] = kc ? gi % SPLIT_KG : gi / ROWS;
+      rok[r] = r0 + row[r] < nrows && (EXACT || tid < NG);
+      ptr[r] = kc ? base + (int64_t)(r0 + row[r]) * ld + kg[r]
+                  : base + (int64_t)kg[r] * ld + (r0 + row[r]);
     }
   }
 
-  template <int LDK>
-  __device__ __forceinline__ void store(const Seg& g, __bf16 (*Xh)[BM][LDK], __bf16 (*Zh)[BN][LDK],
-                                        int tid) {
+  // Global loads of the K tile starting at k0 (kleft = K - k0 values remain).
+  __device__ __forceinline__ void load(int kleft) {
+    const bool full = kleft >= SPLIT_BK;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      const int i = tid + r * NT;
-      if (i < BM * BK) {
-        const int mm = g.xt ? i % BM : i / BK, kk = g.xt ? i / BM : i % BK;
-        split3(x[r], Xh[0][mm][kk], Xh[1][mm][kk], Xh[2][mm][kk]);
+    for (int r = 0; r < G; ++r) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = rok[r] && (full || kg[r] + SPLIT_KG * e < kleft);
+        v[r][e] = ok ? ptr[r][e * estep] : 0.0;
       }
     }
+  }
+
+  __device__ __forceinline__ void advance() {
 #pragma unroll
-    for (int r = 0; r < NZ; ++r) {
-      const int i = tid + r * NT;
-      if (i < BN * BK) {
-        const int nn = g.zt ? i / BK : i % BN, kk = g.zt ? i % BK : i / BN;
-        split3(z[r], Zh[0][nn][kk], Zh[1][nn][kk], Zh[2][nn][kk]);
-      }
+    for (int r = 0; r < G; ++r) ptr[r] += tstep;
+  }
+
+  // Split and store into the three slice planes sh[sl][ROWS][SPLIT_LDK].
+  __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][SPLIT_LDK], int tid) {
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      if (!EXACT && tid >= NG) continue;
+      uint32_t w0[4], w1[4], w2[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) split_pair(v[r][2 * q], v[r][2 * q + 1], w0[q], w1[q], w2[q]);
+      const u4v s0 = {w0[0], w0[1], w0[2], w0[3]};
+      const u4v s1 = {w1[0], w1[1], w1[2], w1[3]};
+      const u4v s2 = {w2[0], w2[1], w2[2], w2[3]};
+      *reinterpret_cast<u4v*>(&sh[0][row[r]][8 * kg[r]]) = s0;
+      *reinterpret_cast<u4v*>(&sh[1][row[r]][8 * kg[r]]) = s1;
+      *reinterpret_cast<u4v*>(&sh[2][row[r]][8 * kg[r]]) = s2;
     }
   }
 };
+
+template <int BM, int BN>
+constexpr int split_nbuf() {
+  return 2 * 3 * (BM + BN) * SPLIT_LDK * 2 <= 160 * 1024 ? 2 : 1;
+}
 
 template <int BM, int BN, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
     Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
     const Tile* __restrict__ tiles, int64_t ntiles) {
   constexpr int NT = 64 * WGM * WGN;
-  constexpr int BK = SPLIT_BK, LDK = BK + 8;
+  constexpr int NB = split_nbuf<BM, BN>();
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 32, FN = WN / 32;
   static_assert(FM >= 1 && FN >= 1, "tile shape");
-  __shared__ __attribute__((aligned(16))) __bf16 Xh[3][BM][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Zh[3][BN][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Xh[NB][3][BM][SPLIT_LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Zh[NB][3][BN][SPLIT_LDK];
 
   const int64_t lt = xcd_remap_s(blockIdx.x, ntiles);
   const Tile t = tiles[lt];
   const Prob p = probs[t.prob];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WGN, wn = wave % WGN;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // Output sub-tile of this wave, rotated by block so that the waves an edge
+  // tile leaves idle fall on different SIMDs from block to block.
+  constexpr int NW = WGM * WGN;
+  const int role = (wave + 2 * (int)(blockIdx.x & 3)) % NW;
+  const int wm = role / WGN, wn = role % WGN;
   const int m0 = t.tm * BM, n0 = t.tn * BN;
   const int fr = lane & 31, fk = (lane >> 5) * 8;
+  // a wave whose output rows or columns all lie outside the problem issues
+  // no fragment reads or MFMAs
+  const bool active = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
 
   f16v acc[FM][FN];
   double acc64[FM][FN][16];
@@ -128,14 +180,20 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
 
   const int s_end = p.seg0 + p.nseg;
   if (p.nseg > 0) {
-    SplitRegs<BM, BN, NT> regs;
-    int s = p.seg0, k0 = 0, since_flush = 0;
+    Stager<BM, NT> xs;
+    Stager<BN, NT> zs;
+    int s = p.seg0, k0 = 0, since_flush = 0, buf = 0;
     Seg g = segs[s];
-    regs.load(g, bases.p[g.xbuf] + g.xoff, bases.p[g.zbuf] + g.zoff, 0, m0, n0, p.M, p.N, tid);
+    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
+    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+    xs.load(g.K);
+    zs.load(g.K);
+    xs.store(Xh[0], tid);
+    zs.store(Zh[0], tid);
+    __syncthreads();
     while (true) {
-      regs.template store<LDK>(g, Xh, Zh, tid);
-      __syncthreads();
-      int s2 = s, k2 = k0 + BK;
+      // next (segment, K tile) position; its global loads go out first
+      int s2 = s, k2 = k0 + SPLIT_BK;
       Seg g2 = g;
       if (k2 >= g.K) {
         ++s2;
@@ -143,20 +201,30 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
         if (s2 < s_end) g2 = segs[s2];
       }
       const bool more = s2 < s_end;
-      if (more)
-        regs.load(g2, bases.p[g2.xbuf] + g2.xoff, bases.p[g2.zbuf] + g2.zoff, k2, m0, n0, p.M, p.N,
-                  tid);
+      const bool seg_end = s2 != s;
+      if (more) {
+        if (seg_end) {
+          xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
+          zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
+        } else {
+          xs.advance();
+          zs.advance();
+        }
+        xs.load(g2.K - k2);
+        zs.load(g2.K - k2);
+      }
+      const int cb = NB == 2 ? buf : 0;
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 16) {
+      for (int kk = 0; kk < (active ? SPLIT_BK : 0); kk += 16) {
         bf8 a[3][FM], b[3][FN];
 #pragma unroll
         for (int sl = 0; sl < 3; ++sl) {
 #pragma unroll
           for (int i = 0; i < FM; ++i)
-            a[sl][i] = *reinterpret_cast<const bf8*>(&Xh[sl][wm * WM + i * 32 + fr][kk + fk]);
+            a[sl][i] = *reinterpret_cast<const bf8*>(&Xh[cb][sl][wm * WM + i * 32 + fr][kk + fk]);
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            b[sl][j] = *reinterpret_cast<const bf8*>(&Zh[sl][wn * WN + j * 32 + fr][kk + fk]);
+            b[sl][j] = *reinterpret_cast<const bf8*>(&Zh[cb][sl][wn * WN + j * 32 + fr][kk + fk]);
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -171,20 +239,27 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
           }
       }
-      if (++since_flush == SPLIT_FLUSH || !more) {
+      if (more) {
+        if (NB == 1) __syncthreads();  // every wave is done with the only buffer
+        xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid);
+        zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid);
+      }
+      if (++since_flush == SPLIT_FLUSH || seg_end) {
         since_flush = 0;
+        const double al = g.alpha;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              acc64[i][j][v] += (double)acc[i][j][v];
+              acc64[i][j][v] += al * (double)acc[i][j][v];
               acc[i][j][v] = 0.f;
             }
       }
       if (!more) break;
-      __syncthreads();  // every wave is done with the LDS tile before it is overwritten
+      __syncthreads();
+      buf ^= 1;
       s = s2;
       k0 = k2;
       g = g2;
@@ -206,7 +281,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
         }
       }
 }
-
 dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                               const Tile* tiles, hipStream_t s) {
   if (l.ntiles <= 0) return DMRG_OK;
@@ -226,7 +300,7 @@ dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs
       gemm_split_kernel<128, 128, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
     case CFG_F64_256x128:
-      gemm_split_kernel<256, 128, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      gemm_split_kernel<256, 128, 4, 4><<<grid, 1024, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
     default:
       return fail(DMRG_EINVAL, "unknown tile configuration");

@@ -266,7 +266,7 @@ extern "C" {
 const char* dmrg_last_error(void) { return g_last_error.c_str(); }
 
 const char* dmrg_build_info(void) {
-  return "dmrg_heff gfx950: FP64 MFMA 16x16x4 grouped GEMM, BF16x3 split MFMA 16x16x32";
+  return "dmrg_heff gfx950: FP64 MFMA 16x16x4 grouped GEMM, BF16x3 split MFMA 32x32x16";
 }
 
 dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx_t* out) {
