@@ -310,12 +310,13 @@ __global__ void subtract_kernel(const double* __restrict__ V, const double* __re
   }
 }
 
-// t /= ||t|| (norm^2 in dots[0]); flag a vanished correction.
+// t /= ||t|| (norm^2 in dots[0]); a norm below `floor` flags a vanished
+// correction.
 __global__ void normalize_kernel(const double* __restrict__ dots, DavState* st, int64_t n,
-                                 double* __restrict__ t) {
+                                 double* __restrict__ t, double floor) {
   const double nrm = sqrt(dots[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->stalled = !(nrm >= 1e-10);
-  if (!(nrm >= 1e-10)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->stalled = !(nrm >= floor);
+  if (!(nrm >= floor)) return;
   const double inv = 1.0 / nrm;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     t[e] *= inv;
@@ -516,6 +517,11 @@ dmrg_status stage_b(dmrg_dav_s* d, hipStream_t s) {
   restart_copy_kernel<<<g, 256, 0, s>>>(d->RW, d->st, kmax, (int64_t)keep * d->n, d->W);
   restart_finish_kernel<<<1, 256, 0, s>>>(d->st, kmax, keep, d->G);
   precond_kernel<<<g, 256, 0, s>>>(d->r, d->diag, d->st, d->n, d->t);
+  // unit correction first, so that the test after orthogonalisation is
+  // relative: it stalls only when t lies in the subspace to ~1e-12
+  scalar_dot_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(d->t, d->t, d->n, d->partial);
+  finish_scalar_kernel<<<1, RED_THREADS, 0, s>>>(d->partial, RED_BLOCKS, d->dots);
+  normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, d->n, d->t, 1e-300);
   DMRG_HIP(hipGetLastError());
   for (int pass = 0; pass < 2; ++pass) {
     dmrg_status st = multidot(d, d->V, d->t, 0, s);
@@ -525,7 +531,7 @@ dmrg_status stage_b(dmrg_dav_s* d, hipStream_t s) {
   }
   scalar_dot_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(d->t, d->t, d->n, d->partial);
   finish_scalar_kernel<<<1, RED_THREADS, 0, s>>>(d->partial, RED_BLOCKS, d->dots);
-  normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, d->n, d->t);
+  normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, d->n, d->t, 1e-12);
   DMRG_HIP(hipGetLastError());
   return expand(d, s);
 }
@@ -630,7 +636,7 @@ dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts, const
   }
   scalar_dot_kernel<<<RED_BLOCKS, RED_THREADS, 0, s>>>(d->t, d->t, n, d->partial);
   finish_scalar_kernel<<<1, RED_THREADS, 0, s>>>(d->partial, RED_BLOCKS, d->dots);
-  normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, n, d->t);
+  normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, n, d->t, 1e-300);
   DMRG_HIP(hipGetLastError());
   if ((st = expand(d.get(), s)) != DMRG_OK) return st;
   d->matvecs = 1;

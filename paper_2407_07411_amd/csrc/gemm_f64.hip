@@ -34,70 +34,80 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// Registers holding one K tile of X (BM x BK) and Z (BK x BN) in flight.
-template <int BM, int BN, int BK, int NT>
-struct TileRegs {
-  static constexpr int NX = (BM * BK + NT - 1) / NT;
-  static constexpr int NZ = (BN * BK + NT - 1) / NT;
-  double x[NX];
-  double z[NZ];
+// Buffer resource over one operand block, advanced in K by the scalar base:
+// per-lane offsets stay fixed for a whole segment, so a K tile's loads cost no
+// vector address arithmetic.  Offsets at or beyond num_records read as zero
+// (hardware range check), which pads rows outside the problem and the K tail.
+constexpr uint32_t OOB = 0xffffffffu;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
 
-  __device__ __forceinline__ void load(const Seg& g, const double* __restrict__ X,
-                                       const double* __restrict__ Z, int k0, int m0, int n0, int M,
-                                       int N, int tid) {
+// One operand's share of a K tile (ROWS x BK values) for one thread: N
+// values, element r at tile row row + r * drow and tile column kk + r * dkk.
+// kc: element (row, k) of the operand sits at base + row * ld + k (contiguous
+// in K; consecutive lanes take consecutive k); otherwise at base + k * ld +
+// row (consecutive lanes take consecutive rows).  LDS holds the tile K-major:
+// S[k][row].
+template <int ROWS, int BK, int NT>
+struct Stage {
+  static constexpr int N = ROWS * BK / NT;
+  static_assert(ROWS * BK % NT == 0 && NT % BK == 0 && NT % ROWS == 0, "staging shape");
+  const double* base;  // uniform: the block's first row at the current k0
+  int64_t kstep;       // uniform: elements between K tiles
+  uint32_t off[N];     // byte offsets from base (OOB for rows outside the problem)
+  int kk, lds;         // K column of element 0; LDS index of element 0
+  bool kc;
+  double v[N];
+
+  __device__ __forceinline__ void setup(const double* seg, int ld, bool kc_, int r0, int nrows,
+                                        int tid) {
+    kc = kc_;
+    const int row = kc ? tid / BK : tid % ROWS;
+    kk = kc ? tid % BK : tid / ROWS;
+    lds = kk * (ROWS + 1) + row;
+    if (kc) {
+      base = seg + (int64_t)r0 * ld;
+      kstep = BK;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      const int i = tid + r * NT;
-      int mm, kk;
-      if (!g.xt) {
-        mm = i / BK;
-        kk = i % BK;
-      } else {
-        mm = i % BM;
-        kk = i / BM;
+      for (int r = 0; r < N; ++r) {
+        const int rr = row + r * (NT / BK);
+        off[r] = r0 + rr < nrows ? (uint32_t)(rr * ld + kk) * 8u : OOB;
       }
-      const int m = m0 + mm, k = k0 + kk;
-      const bool ok = i < BM * BK && m < M && k < g.K;
-      x[r] = ok ? X[g.xt ? (int64_t)k * g.ldx + m : (int64_t)m * g.ldx + k] : 0.0;
-    }
+    } else {
+      base = seg + r0;
+      kstep = (int64_t)BK * ld;
+      const bool ok = r0 + row < nrows;
 #pragma unroll
-    for (int r = 0; r < NZ; ++r) {
-      const int i = tid + r * NT;
-      int nn, kk;
-      if (!g.zt) {
-        nn = i % BN;
-        kk = i / BN;
-      } else {
-        nn = i / BK;
-        kk = i % BK;
-      }
-      const int n = n0 + nn, k = k0 + kk;
-      const bool ok = i < BN * BK && n < N && k < g.K;
-      z[r] = ok ? Z[g.zt ? (int64_t)n * g.ldz + k : (int64_t)k * g.ldz + n] : 0.0;
+      for (int r = 0; r < N; ++r) off[r] = ok ? (uint32_t)((kk + r * (NT / ROWS)) * ld + row) * 8u : OOB;
     }
   }
 
-  __device__ __forceinline__ void store(const Seg& g, double alpha, double (*Xs)[BM + 1],
-                                        double (*Zs)[BN + 1], int tid) {
+  // kleft = K - k0 values remain in the segment
+  __device__ __forceinline__ void load(int kleft) {
+    const __amdgpu_buffer_rsrc_t rs = operand_rsrc(base);
+    if (kleft >= BK) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      const int i = tid + r * NT;
-      if (i < BM * BK) {
-        if (!g.xt)
-          Xs[i % BK][i / BK] = alpha * x[r];
-        else
-          Xs[i / BM][i % BM] = alpha * x[r];
+      for (int r = 0; r < N; ++r)
+        v[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off[r], 0, 0));
+    } else {
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        const int k = kc ? kk : kk + r * (NT / ROWS);
+        v[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, k < kleft ? off[r] : OOB, 0, 0));
       }
     }
+  }
+
+  __device__ __forceinline__ void advance() { base += kstep; }
+
+  __device__ __forceinline__ void store(double* S, double alpha) const {
+    if (kc) {
 #pragma unroll
-    for (int r = 0; r < NZ; ++r) {
-      const int i = tid + r * NT;
-      if (i < BN * BK) {
-        if (!g.zt)
-          Zs[i / BN][i % BN] = z[r];
-        else
-          Zs[i % BK][i / BK] = z[r];
-      }
+      for (int r = 0; r < N; ++r) S[lds + r * (NT / BK)] = alpha * v[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < N; ++r) S[lds + r * (NT / ROWS) * (ROWS + 1)] = alpha * v[r];
     }
   }
 };
@@ -135,15 +145,20 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
 
   const int s_end = p.seg0 + p.nseg;
   if (p.nseg > 0) {
-    TileRegs<BM, BN, BK, NT> regs;
+    Stage<BM, BK, NT> xs;
+    Stage<BN, BK, NT> zs;
     int s = p.seg0, k0 = 0;
     Seg g = segs[s];
-    regs.load(g, bases.p[g.xbuf] + g.xoff, bases.p[g.zbuf] + g.zoff, 0, m0, n0, p.M, p.N, tid);
-    regs.store(g, g.alpha, Xs[0], Zs[0], tid);
+    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
+    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+    xs.load(g.K);
+    zs.load(g.K);
+    xs.store(&Xs[0][0][0], g.alpha);
+    zs.store(&Zs[0][0][0], 1.0);
     __syncthreads();
     int buf = 0;
     while (true) {
-      // next (segment, K tile) position
+      // next (segment, K tile) position; its global loads go out first
       int s2 = s, k2 = k0 + BK;
       Seg g2 = g;
       if (k2 >= g.K) {
@@ -152,9 +167,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
         if (s2 < s_end) g2 = segs[s2];
       }
       const bool more = s2 < s_end;
-      if (more)
-        regs.load(g2, bases.p[g2.xbuf] + g2.xoff, bases.p[g2.zbuf] + g2.zoff, k2, m0, n0, p.M, p.N,
-                  tid);
+      if (s2 != s) {  // past the last segment g2 == g: harmless, nothing is loaded
+        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
+        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
+      } else {
+        xs.advance();
+        zs.advance();
+      }
+      if (more) {
+        xs.load(g2.K - k2);
+        zs.load(g2.K - k2);
+      }
       // edge tiles: a wave whose output rows or columns all lie outside the
       // problem issues no LDS reads or MFMAs
       if (active) {
@@ -174,7 +197,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
       }
       if (!more) break;
       // the other buffer was last read before the previous barrier
-      regs.store(g2, g2.alpha, Xs[buf ^ 1], Zs[buf ^ 1], tid);
+      xs.store(&Xs[buf ^ 1][0][0], g2.alpha);
+      zs.store(&Zs[buf ^ 1][0][0], 1.0);
       __syncthreads();
       buf ^= 1;
       s = s2;

@@ -64,55 +64,68 @@ __device__ __forceinline__ void split_pair(double a, double b, uint32_t& s0, uin
   s2 = pk_bits(h2);
 }
 
+constexpr uint32_t OOB_S = 0xffffffffu;
+
 // The 8-value groups of one operand (ROWS x BK per K tile) that a thread
 // stages: up to G groups, group r is gi = tid + r * NT < ROWS * SPLIT_KG.
+// Loads go through a buffer resource whose scalar base walks K; per-lane
+// offsets are fixed for a segment and the step between the 8 values of a group
+// is a scalar offset, so full K tiles cost no vector address arithmetic.  Rows
+// outside the problem are clamped to its last row: they feed only outputs
+// that are never stored.  In the K tail, offsets at or beyond num_records
+// read as zero (with no scalar offset added).
 template <int ROWS, int NT>
 struct Stager {
   static constexpr int NG = ROWS * SPLIT_KG;
   static constexpr int G = (NG + NT - 1) / NT;
   static constexpr bool EXACT = NG % NT == 0;
   static_assert(EXACT || G == 1, "staging shape");
-  const double* ptr[G];  // address of k = k0 + kg for the group's row
+  const double* base;  // uniform: the block's first row at the current k0
+  int64_t tstep;       // uniform: elements between K tiles
+  uint32_t estep;      // uniform: bytes between value e and e + 1 of a group
+  uint32_t off[G];     // byte offset of value 0 of each group (OOB outside the problem)
   int row[G], kg[G];
-  bool rok[G];
-  int64_t estep;         // address step between e and e + 1
-  int64_t tstep;         // address step between K tiles
   double v[G][8];
 
   // kc: the operand is contiguous in K (element (row, k) at base + row*ld + k);
   // otherwise it is contiguous in the row index (base + k*ld + row).
-  __device__ __forceinline__ void setup(const double* base, int ld, bool kc, int r0, int nrows,
+  __device__ __forceinline__ void setup(const double* seg, int ld, bool kc, int r0, int nrows,
                                         int tid) {
-    estep = kc ? (int64_t)SPLIT_KG : (int64_t)SPLIT_KG * ld;
+    base = kc ? seg + (int64_t)r0 * ld : seg + r0;
     tstep = kc ? (int64_t)SPLIT_BK : (int64_t)SPLIT_BK * ld;
+    estep = kc ? 8u * SPLIT_KG : 8u * SPLIT_KG * (uint32_t)ld;
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const int gi = EXACT ? tid + r * NT : min(tid, NG - 1);
       row[r] = kc ? gi / SPLIT_KG : gi % ROWS;
       kg[r] = kc ? gi % SPLIT_KG : gi / ROWS;
-      rok[r] = r0 + row[r] < nrows && (EXACT || tid < NG);
-      ptr[r] = kc ? base + (int64_t)(r0 + row[r]) * ld + kg[r]
-                  : base + (int64_t)kg[r] * ld + (r0 + row[r]);
+      const int rc = min(row[r], nrows - 1 - r0);
+      off[r] = kc ? (uint32_t)(rc * ld + kg[r]) * 8u : (uint32_t)(kg[r] * ld + rc) * 8u;
     }
   }
 
   // Global loads of the K tile starting at k0 (kleft = K - k0 values remain).
   __device__ __forceinline__ void load(int kleft) {
-    const bool full = kleft >= SPLIT_BK;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, 0x7fffffff, 0x00020000);
+    if (kleft >= SPLIT_BK) {
 #pragma unroll
-    for (int r = 0; r < G; ++r) {
+      for (int r = 0; r < G; ++r)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const bool ok = rok[r] && (full || kg[r] + SPLIT_KG * e < kleft);
-        v[r][e] = ok ? ptr[r][e * estep] : 0.0;
-      }
+        for (int e = 0; e < 8; ++e)
+          v[r][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off[r], e * estep, 0));
+    } else {
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t o = kg[r] + SPLIT_KG * e < kleft ? off[r] + e * estep : OOB_S;
+          v[r][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0));
+        }
     }
   }
 
-  __device__ __forceinline__ void advance() {
-#pragma unroll
-    for (int r = 0; r < G; ++r) ptr[r] += tstep;
-  }
+  __device__ __forceinline__ void advance() { base += tstep; }
 
   // Split and store into the three slice planes sh[sl][ROWS][SPLIT_LDK].
   __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][SPLIT_LDK], int tid) {
@@ -202,14 +215,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
       }
       const bool more = s2 < s_end;
       const bool seg_end = s2 != s;
+      if (seg_end) {  // past the last segment g2 == g: harmless, nothing is loaded
+        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
+        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
+      } else {
+        xs.advance();
+        zs.advance();
+      }
       if (more) {
-        if (seg_end) {
-          xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
-          zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
-        } else {
-          xs.advance();
-          zs.advance();
-        }
         xs.load(g2.K - k2);
         zs.load(g2.K - k2);
       }

@@ -16,9 +16,19 @@ using namespace dmrg;
 
 namespace {
 
-int64_t env_workspace_doubles() {
+// Intermediate-workspace budget: DMRG_HEFF_WORKSPACE_MB, else 30% of the
+// device memory free at plan time, between 1 and 32 GiB.  Fewer, larger waves
+// mean fewer launch tails; only what the largest wave needs is allocated.
+int64_t workspace_budget_doubles() {
   const char* s = std::getenv("DMRG_HEFF_WORKSPACE_MB");
-  int64_t mb = s ? std::atoll(s) : 8192;
+  int64_t mb = 8192;
+  if (s) {
+    mb = std::atoll(s);
+  } else {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+      mb = std::min<int64_t>(32768, std::max<int64_t>(1024, (int64_t)(0.3 * (double)free_b) >> 20));
+  }
   if (mb < 1) mb = 1;
   return mb * (1 << 20) / 8;
 }
@@ -549,7 +559,7 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   dmrg_status st = build_items(h.get(), n_terms, terms);
   if (st != DMRG_OK) return st;
   count_work(h.get());
-  h->work_budget = env_workspace_doubles();
+  h->work_budget = workspace_budget_doubles();
   if ((st = build_forward(h.get(), cfg_from_env())) != DMRG_OK) return st;
   {
     int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0,

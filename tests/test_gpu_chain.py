@@ -49,7 +49,9 @@ def test_l8_centre_step_is_fci(ctx):
     e_fci = fci_energy(h, V, 4, 4)
     ch = Chain(ctx, h, V, 8, 0, D=64, seed=7)
     steps = run_sweeps(ch, 2)
-    print([(s["site"], round(s["energy"] - e_fci, 10), s["trunc_err"]) for s in steps], flush=True)
+    for s in steps:
+        print(s["site"], round(s["energy"] - e_fci, 10), s["trunc_err"], s["converged"], s["iters"],
+              s["residual"], flush=True)
     for s in steps:
         assert s["converged"]
         assert s["energy"] >= e_fci - 1e-9
