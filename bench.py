@@ -65,7 +65,7 @@ def profiled_traffic(kernel, workload):
             if line.startswith("sources_sha256:"):
                 digest = line.split(":", 1)[1].strip()
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) >= 2 and cells[0] == f"`{kernel}`":
+            if len(cells) >= 2 and cells[0].strip("`").replace(" ", "") == kernel.replace(" ", ""):
                 try:
                     val = float(cells[-1])
                 except ValueError:
