@@ -199,3 +199,49 @@ def count_flops(prob):
                 total += min(2 * dl2 * dl * dr + 2 * dl2 * dr * dr2,
                              2 * dl * dr * dr2 + 2 * dl2 * dl * dr2)
     return total
+
+
+def _stored_rows(pool, spec, trans, rows):
+    """Rows `rows` of a stored block, or of its transpose, as float64 numpy.
+    The pool may be a numpy array or a (device) tensor: only the needed
+    slices are copied."""
+    kind, off, nr, nc = spec
+    out = []
+    for r in rows:
+        if not trans:
+            v = pool[off + r * nc: off + (r + 1) * nc]
+        else:
+            v = pool[off + r: off + nr * nc: nc]
+        out.append(_np(v).astype(np.float64))
+    return np.stack(out) if out else np.zeros((0, nr if trans else nc))
+
+
+def heff_entries(prob, b, rows, cols, psi=None):
+    """Entries y[b][rows][:, cols] of y = H_eff psi by the same definition as
+    heff_apply (left sector b of the output; row and column indices inside
+    that block), plus the sum of the absolute values of every product that
+    enters each entry (the scale of its rounding error).
+
+    Per item: (A[rows, :] @ Psi_a) @ B[cols, :]^T, so a whole-size problem can
+    be sampled without forming any full output block."""
+    lay = layout_of(prob)
+    pools = {"L": prob.left_pool, "R": prob.right_pool}
+    x = _np(prob.psi if psi is None else psi).astype(np.float64)
+    rows, cols = list(rows), list(cols)
+    val = np.zeros((len(rows), len(cols)))
+    mag = np.zeros((len(rows), len(cols)))
+    for t in prob.terms:
+        for (a, bb, A, tA, B, tB, alpha) in term_items(lay, t):
+            if bb != b:
+                continue
+            X = lay.block(x, a)
+            XA = X[rows, :] if A is None else _stored_rows(pools[A[0]], A, tA, rows) @ X
+            XAabs = np.abs(X[rows, :]) if A is None else np.abs(_stored_rows(pools[A[0]], A, tA, rows)) @ np.abs(X)
+            if B is None:
+                v, m = XA[:, cols], XAabs[:, cols]
+            else:
+                Bc = _stored_rows(pools[B[0]], B, tB, cols)
+                v, m = XA @ Bc.T, XAabs @ np.abs(Bc).T
+            val += alpha * v
+            mag += abs(alpha) * m
+    return val, mag

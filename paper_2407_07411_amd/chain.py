@@ -30,10 +30,14 @@ class Chain:
         check(lib().dmrg_chain_create(ctx.h if ctx is not None else None, L, _p(h), _p(V), int(n_elec),
                                       int(two_sz), int(D), int(seed), byref(out)))
         self.h = out
+        self._destroy = lib().dmrg_chain_destroy
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().dmrg_chain_destroy(self.h)
+        # the destroy entry point is bound at construction: module globals
+        # may already be gone when the interpreter shuts down
+        fn = getattr(self, "_destroy", None)
+        if getattr(self, "h", None) and fn is not None:
+            fn(self.h)
             self.h = None
 
     def step(self, l, direction, tol=1e-8, max_iter=200, max_subspace=24, restart_keep=2):

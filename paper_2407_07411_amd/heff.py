@@ -38,13 +38,17 @@ class Context:
         h = c_void_p()
         check(lib().dmrg_ctx_create(dev.index, c_void_p(torch.cuda.current_stream(dev).cuda_stream), byref(h)))
         self.h = h
+        self._destroy = lib().dmrg_ctx_destroy
 
     def sync_stream(self):
         check(lib().dmrg_ctx_set_stream(self.h, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().dmrg_ctx_destroy(self.h)
+        # the destroy entry point is bound at construction: module globals
+        # may already be gone when the interpreter shuts down
+        fn = getattr(self, "_destroy", None)
+        if getattr(self, "h", None) and fn is not None:
+            fn(self.h)
             self.h = None
 
 
@@ -57,10 +61,14 @@ class Basis:
         check(lib().dmrg_basis_create(ctx.h, int(len(dim)), qn.ctypes.data_as(ctypes.POINTER(c_int32)),
                                       dim.ctypes.data_as(ctypes.POINTER(c_int64)), byref(h)))
         self.h = h
+        self._destroy = lib().dmrg_basis_destroy
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().dmrg_basis_destroy(self.h)
+        # the destroy entry point is bound at construction: module globals
+        # may already be gone when the interpreter shuts down
+        fn = getattr(self, "_destroy", None)
+        if getattr(self, "h", None) and fn is not None:
+            fn(self.h)
             self.h = None
 
 
@@ -107,11 +115,15 @@ class Heff:
                                      _ptr(self.left_pool), self.left_pool.numel(),
                                      _ptr(self.right_pool), self.right_pool.numel(), int(prec), byref(h)))
         self.h = h
+        self._destroy = lib().dmrg_heff_destroy
         self.size = int(lib().dmrg_heff_size(h))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().dmrg_heff_destroy(self.h)
+        # the destroy entry point is bound at construction: module globals
+        # may already be gone when the interpreter shuts down
+        fn = getattr(self, "_destroy", None)
+        if getattr(self, "h", None) and fn is not None:
+            fn(self.h)
             self.h = None
 
     def set_precision(self, prec):

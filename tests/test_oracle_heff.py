@@ -176,3 +176,23 @@ def test_flop_count_by_hand():
                    torch.from_numpy(rng.standard_normal(9)), torch.from_numpy(rng.standard_normal(16)),
                    torch.zeros(12, dtype=torch.float64))
     assert count_flops(prob) == 2 * 168
+
+
+@pytest.mark.parametrize("seed,D,two_sz", [(4, 6, 0), (5, 5, 2)])
+def test_sampled_entries_equal_kron_assembly(seed, D, two_sz):
+    """heff_entries (used to sample whole-size problems) against the
+    independent Kronecker assembly, on every block and a ragged sample."""
+    from oracle.heff import heff_entries
+    prob = tiny_problem(seed=seed, D=D, two_sz=two_sz, pairs=2)
+    lay = layout_of(prob)
+    x = prob.psi.numpy()
+    y = kron_dense(prob) @ x
+    for b in lay.partner:
+        e = lay.partner[b]
+        nr, nc = int(lay.Ld[b]), int(lay.Rd[e])
+        rows = list(range(nr))[::2] or [0]
+        cols = list(range(nc))[::-1]
+        val, mag = heff_entries(prob, b, rows, cols)
+        ref = lay.block(y, b)[np.ix_(rows, cols)]
+        assert np.abs(val - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+        assert np.all(mag >= np.abs(val) - 1e-15)
