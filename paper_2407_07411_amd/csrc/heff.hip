@@ -106,6 +106,12 @@ dmrg_status Program::validate(const int64_t* len) const {
 }
 
 void Program::release() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  events.clear();
+  for (int i = 0; i < 2; ++i) {
+    if (side[i]) (void)hipStreamDestroy(side[i]);
+    side[i] = nullptr;
+  }
   if (d_probs) (void)hipFree(d_probs);
   if (d_segs) (void)hipFree(d_segs);
   if (d_tiles) (void)hipFree(d_tiles);
@@ -118,7 +124,25 @@ void Program::release() {
   d_red_parts = nullptr;
 }
 
+// Side streams (default priority, non-blocking) and the events of one run,
+// created with the plan so that no creation call falls inside a graph capture.
+dmrg_status Program::prepare_concurrent() {
+  int nphase = 0;
+  for (const Launch& l : launches) nphase = std::max(nphase, l.phase + 1);
+  for (int i = 0; i < 2; ++i)
+    if (!side[i]) DMRG_HIP(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
+  const size_t need = 4 * (size_t)nphase + 1;
+  while (events.size() < need) {
+    hipEvent_t e;
+    DMRG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    events.push_back(e);
+  }
+  concurrent = true;
+  return DMRG_OK;
+}
+
 dmrg_status Program::run(const Bases& b, hipStream_t s, int precision) const {
+  if (concurrent && s != nullptr) return run_concurrent(b, s, precision);
   for (const Launch& l : launches) {
     Launch x = l;
     x.split = precision;
@@ -126,6 +150,85 @@ dmrg_status Program::run(const Bases& b, hipStream_t s, int precision) const {
                                          : launch_gemm(x, b, d_probs, d_segs, d_tiles, s);
     if (st != DMRG_OK) return st;
   }
+  return DMRG_OK;
+}
+
+namespace {
+dmrg_status launch_one(const Launch& l, const Bases& b, const Program& P, hipStream_t s, int precision) {
+  Launch x = l;
+  x.split = precision;
+  return l.cfg == CFG_REDUCE ? launch_reduce(x, b, P.d_reds, P.d_red_parts, s)
+                             : launch_gemm(x, b, P.d_probs, P.d_segs, P.d_tiles, s);
+}
+}  // namespace
+
+// Stream s (the caller's) runs the largest tile shape of every phase; side[0]
+// runs the smaller shapes of the same phase (fork after the previous phase,
+// join before the next); side[1] runs a K-split reduction next to the
+// following phase when that phase writes intermediates only (its outputs and
+// the partial sums are not touched there), and the phase after it waits for
+// the reduction.  Every side stream is joined into s before returning, so the
+// caller sees one ordered operation (and a graph capture on s closes).
+dmrg_status Program::run_concurrent(const Bases& b, hipStream_t s, int precision) const {
+  size_t ev = 0;
+  hipEvent_t pending = nullptr;  // reduction still running on side[1]
+  int pending_phase = -1;
+  for (size_t i = 0; i < launches.size();) {
+    const int ph = launches[i].phase;
+    size_t j = i;
+    while (j < launches.size() && launches[j].phase == ph) ++j;
+    if (pending && ph - pending_phase >= 2) {
+      DMRG_HIP(hipStreamWaitEvent(s, pending, 0));
+      pending = nullptr;
+    }
+    std::vector<const Launch*> gemms;
+    const Launch* red = nullptr;
+    for (size_t k = i; k < j; ++k) {
+      if (launches[k].cfg == CFG_REDUCE) red = &launches[k];
+      else gemms.push_back(&launches[k]);
+    }
+    // launches are stored largest tile shape first
+    if (gemms.size() > 1) {
+      hipEvent_t fork = events[ev++], done = events[ev++];
+      DMRG_HIP(hipEventRecord(fork, s));
+      DMRG_HIP(hipStreamWaitEvent(side[0], fork, 0));
+      for (size_t k = 1; k < gemms.size(); ++k) {
+        dmrg_status st = launch_one(*gemms[k], b, *this, side[0], precision);
+        if (st != DMRG_OK) return st;
+      }
+      DMRG_HIP(hipEventRecord(done, side[0]));
+      if (!gemms.empty()) {
+        dmrg_status st = launch_one(*gemms[0], b, *this, s, precision);
+        if (st != DMRG_OK) return st;
+      }
+      DMRG_HIP(hipStreamWaitEvent(s, done, 0));
+    } else if (!gemms.empty()) {
+      dmrg_status st = launch_one(*gemms[0], b, *this, s, precision);
+      if (st != DMRG_OK) return st;
+    }
+    if (red) {
+      const bool next_intermediate = j < launches.size() && launches[j].ptype == 0;
+      if (next_intermediate) {
+        if (pending) {  // at most one reduction in flight
+          DMRG_HIP(hipStreamWaitEvent(s, pending, 0));
+          pending = nullptr;
+        }
+        hipEvent_t fork = events[ev++], done = events[ev++];
+        DMRG_HIP(hipEventRecord(fork, s));
+        DMRG_HIP(hipStreamWaitEvent(side[1], fork, 0));
+        dmrg_status st = launch_one(*red, b, *this, side[1], precision);
+        if (st != DMRG_OK) return st;
+        DMRG_HIP(hipEventRecord(done, side[1]));
+        pending = done;
+        pending_phase = ph;
+      } else {
+        dmrg_status st = launch_one(*red, b, *this, s, precision);
+        if (st != DMRG_OK) return st;
+      }
+    }
+    i = j;
+  }
+  if (pending) DMRG_HIP(hipStreamWaitEvent(s, pending, 0));
   return DMRG_OK;
 }
 
@@ -206,13 +309,15 @@ void ProgramBuilder::close_phase() {
   }
   for (int c = CFG_F64_COUNT - 1; c >= 0; --c) {
     if (per[c].empty()) continue;
-    Launch l{c, 0, (int64_t)prog.tiles.size(), (int64_t)per[c].size()};
+    Launch l{c, 0, (int64_t)prog.tiles.size(), (int64_t)per[c].size(), phase_seq, phase_id};
     prog.tiles.insert(prog.tiles.end(), per[c].begin(), per[c].end());
     prog.launches.push_back(l);
   }
   if (prog.reds.size() > red_first)
-    prog.launches.push_back(Launch{CFG_REDUCE, 0, (int64_t)red_first, (int64_t)(prog.reds.size() - red_first)});
+    prog.launches.push_back(Launch{CFG_REDUCE, 0, (int64_t)red_first,
+                                   (int64_t)(prog.reds.size() - red_first), phase_seq, phase_id});
   phase_first = prog.probs.size();
+  ++phase_seq;
 }
 
 int32_t ProgramBuilder::add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta) {

@@ -89,6 +89,8 @@ struct Launch {
   int32_t split;     // 0 FP64, 1 split BF16x3
   int64_t tile0;
   int64_t ntiles;
+  int32_t phase = 0; // launches of one phase are independent of each other
+  int32_t ptype = 0; // 0: the phase writes intermediates only, 1: outputs
 };
 
 // Long-K problems are cut into K parts that run as separate workgroups: part
@@ -126,6 +128,15 @@ struct Program {
   // length (in doubles) of each buffer id.  Run before the first launch.
   dmrg_status validate(const int64_t* buf_len) const;
   dmrg_status run(const Bases& b, hipStream_t s, int precision) const;
+  // Two-stream execution (set for the forward program): within a phase the
+  // smaller tile shapes run beside the largest one, and a phase's K-split
+  // reduction runs beside the next phase when that one writes intermediates
+  // only.  Needs a non-null caller stream; otherwise launches run in order.
+  bool concurrent = false;
+  mutable hipStream_t side[2] = {nullptr, nullptr};
+  mutable std::vector<hipEvent_t> events;
+  dmrg_status run_concurrent(const Bases& b, hipStream_t s, int precision) const;
+  dmrg_status prepare_concurrent();
 };
 
 dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,

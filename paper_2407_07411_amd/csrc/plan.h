@@ -48,6 +48,7 @@ struct ProgramBuilder {
   size_t phase_first = 0;
   int cfg_override = -1;
   int phase_id = 0;                 // 0: intermediates, 1: sums into the outputs
+  int32_t phase_seq = 0;            // phases closed so far
   const TuneTable* tune = nullptr;
   int32_t add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta);
   void add_seg(int32_t prob, const Seg& s);

@@ -33,6 +33,12 @@ int64_t workspace_budget_doubles() {
   return mb * (1 << 20) / 8;
 }
 
+// DMRG_HEFF_SERIAL=1 runs every launch of a matvec in order on one stream.
+bool serial_from_env() {
+  const char* s = std::getenv("DMRG_HEFF_SERIAL");
+  return s && std::atoi(s) != 0;
+}
+
 int cfg_from_env() {
   const char* s = std::getenv("DMRG_HEFF_TILE");
   if (!s) return -1;
@@ -567,6 +573,10 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
     if ((st = h->fwd.validate(len)) != DMRG_OK) return st;
   }
   if ((st = h->fwd.upload()) != DMRG_OK) return st;
+  if (!serial_from_env() && (st = h->fwd.prepare_concurrent()) != DMRG_OK) {
+    h->fwd.release();
+    return st;
+  }
   if (hipMalloc(&h->part, std::max<int64_t>(h->fwd.part_elems, 1) * sizeof(double)) != hipSuccess) {
     h->part = nullptr;
     h->fwd.release();
@@ -850,6 +860,7 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
     st = h->fwd.validate(len);
   }
   if (st == DMRG_OK) st = h->fwd.upload();
+  if (st == DMRG_OK && !serial_from_env()) st = h->fwd.prepare_concurrent();
   if (st != DMRG_OK) {
     h->fwd.release();
     h->fwd = std::move(old);

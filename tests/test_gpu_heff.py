@@ -188,3 +188,38 @@ def test_split_k_sums(ctx, l24, kchunk, monkeypatch):
     h.adjoint(x, torch.from_numpy(yb).cuda(), gp, None, None)
     pb, _, _ = heff_adjoint(l24, l24.psi.numpy(), yb)
     assert rel(gp.cpu().numpy(), pb) <= TOL
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_stream_phases_match_serial(l24, prec, monkeypatch):
+    """On a caller stream, each phase runs its smaller tile shapes on a side
+    stream next to the largest one, and K-split reductions run next to the
+    following intermediate phase: with many waves, long sums cut in parts and
+    every tile shape in use, the result equals the one-stream order bit for
+    bit (and the oracle), eagerly and from a replayed graph."""
+    from paper_2407_07411_amd.heff import Context, Heff
+    print("case two-stream prec", prec, flush=True)
+    monkeypatch.setenv("DMRG_HEFF_KCHUNK", "300")
+    monkeypatch.setenv("DMRG_HEFF_WORKSPACE_MB", "4")
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    ys = []
+    with torch.cuda.stream(stream):
+        c = Context(0)
+        x = l24.psi.to("cuda")
+        for serial in ("1", "0"):
+            monkeypatch.setenv("DMRG_HEFF_SERIAL", serial)
+            h = Heff(c, l24.Lq, l24.Ld, l24.Rq, l24.Rd, l24.Q, l24.terms, l24.left_pool.to("cuda"),
+                     l24.right_pool.to("cuda"), prec=prec)
+            ys.append(h.apply(x).clone())
+            if serial == "0":
+                ys.append(h.apply(x).clone())
+                h.use_graph(True)
+                for _ in range(3):
+                    ys.append(h.apply(x).clone())
+                h.use_graph(False)
+    torch.cuda.synchronize()
+    for y in ys[1:]:
+        assert torch.equal(ys[0], y)
+    if prec == 0:
+        assert rel(ys[0].cpu().numpy(), heff_apply(l24)) <= TOL
