@@ -151,7 +151,8 @@ int64_t dmrg_heff_workspace_bytes(dmrg_heff_t h);
  * later applies with the same pointers (1) or launch eagerly (0). */
 dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable);
 
-/* Autotuner: times every tile shape (32x32, 64x64, 128x128) on the plan's
+/* Autotuner: times every tile shape (the kernel ids of dmrg_heff_launches;
+ * the split kernels skip 256x128) on the plan's
  * own problems, grouped by phase (intermediates / output sums) and by the
  * (M, N) size class (<=16, 32, 64, 128, 256, 512, larger), keeps the fastest
  * shape per group and rebuilds the plan with it.  The timing runs the
@@ -164,7 +165,8 @@ dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int3
  * n_launches (host) receives their number; when kernel / flops are non-null
  * (host arrays of at least that many entries) they receive each launch's
  * kernel id (FP64 grouped GEMM tiles 0: 32x32, 1: 64x64, 2: 128x128 with 4
- * waves, 3: 128x128 with 8 waves, 4: 256x128 with 8 waves; +16 for the split
+ * waves, 3: 128x128 with 8 waves, 4: 256x128 with 8 waves, 5: 64x128 with 8
+ * waves; +16 for the split
  * precision kernels; 32: the ordered reduction of cut K sums) and its
  * algorithmic FLOPs (2 M N K summed over its problems, 0 for reductions). */
 dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops);

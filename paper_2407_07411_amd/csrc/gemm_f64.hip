@@ -224,7 +224,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
 }
 
 int cfg_bm(int cfg) {
-  return cfg == CFG_F64_32 ? 32 : cfg == CFG_F64_64 ? 64 : cfg == CFG_F64_256x128 ? 256 : 128;
+  return cfg == CFG_F64_32                                ? 32
+         : cfg == CFG_F64_64 || cfg == CFG_F64_64x128     ? 64
+         : cfg == CFG_F64_256x128                         ? 256
+                                                          : 128;
 }
 int cfg_bn(int cfg) { return cfg == CFG_F64_32 ? 32 : cfg == CFG_F64_64 ? 64 : 128; }
 
@@ -249,6 +252,9 @@ dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, cons
       break;
     case CFG_F64_256x128:
       gemm_f64_kernel<256, 128, 16, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_F64_64x128:
+      gemm_f64_kernel<64, 128, 16, 2, 4><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
     default:
       return fail(DMRG_EINVAL, "unknown tile configuration");

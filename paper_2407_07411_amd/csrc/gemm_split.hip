@@ -312,6 +312,9 @@ dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs
     case CFG_F64_128W8:
       gemm_split_kernel<128, 128, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
+    case CFG_F64_64x128:
+      gemm_split_kernel<64, 128, 2, 4><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
     case CFG_F64_256x128:
       gemm_split_kernel<256, 128, 4, 4><<<grid, 1024, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;

@@ -240,9 +240,13 @@ int64_t kchunk_from_env() {
   return v >= 16 ? v : KCHUNK;
 }
 
-// Tile shape for one output matrix.
-int choose_cfg(int M, int N) {
-  if (M >= 96 && N >= 96) return CFG_F64_128W8;
+// Tile shape for one output matrix.  FP64: 64x128 tiles of eight 32x32
+// waves (high occupancy, 64-row padding) measured fastest on sector-shaped
+// sums; split precision: 128x128 (its three BF16 planes make 64x128 tiles
+// LDS-bound at one workgroup per CU).
+int choose_cfg(int M, int N, bool split) {
+  if (split && M >= 96 && N >= 96) return CFG_F64_128W8;
+  if (!split && M >= 40 && N >= 96) return CFG_F64_64x128;
   if (M >= 40 && N >= 40) return CFG_F64_64;
   return CFG_F64_32;
 }
@@ -300,7 +304,7 @@ void ProgramBuilder::close_phase() {
     const Prob& p = prog.probs[pi];
     int cfg = cfg_override;
     if (cfg < 0 && tune) cfg = tune->cfg[phase_id][size_bucket(p.M)][size_bucket(p.N)];
-    if (cfg < 0) cfg = choose_cfg(p.M, p.N);
+    if (cfg < 0) cfg = choose_cfg(p.M, p.N, split);
     prog.probs[pi].pad0 = (uint8_t)phase_id;
     int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
     int tm = (p.M + bm - 1) / bm, tn = (p.N + bn - 1) / bn;

@@ -76,7 +76,8 @@ enum TileCfg : int32_t {
   CFG_F64_128 = 2,     // 128x128 tile, 4 waves
   CFG_F64_128W8 = 3,   // 128x128 tile, 8 waves (two per SIMD)
   CFG_F64_256x128 = 4, // 256x128 tile, 8 waves
-  CFG_F64_COUNT = 5
+  CFG_F64_64x128 = 5,  // 64x128 tile, 8 waves of 32x32 (six waves per SIMD fit)
+  CFG_F64_COUNT = 6
 };
 int cfg_bm(int cfg);
 int cfg_bn(int cfg);

@@ -48,6 +48,7 @@ struct ProgramBuilder {
   size_t phase_first = 0;
   int cfg_override = -1;
   int phase_id = 0;                 // 0: intermediates, 1: sums into the outputs
+  bool split = false;               // tile rule of the split-precision kernels
   int32_t phase_seq = 0;            // phases closed so far
   const TuneTable* tune = nullptr;
   int32_t add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta);
@@ -58,7 +59,7 @@ struct ProgramBuilder {
 dmrg_status heff_apply_eager(struct ::dmrg_heff_s* h, const double* psi, double* y);
 Seg make_seg(uint8_t xbuf, int64_t xoff, int ldx, bool xt, uint8_t zbuf, int64_t zoff, int ldz,
              bool zt, int K, double alpha);
-int choose_cfg(int M, int N);
+int choose_cfg(int M, int N, bool split);
 
 }  // namespace dmrg
 
@@ -76,13 +77,17 @@ struct dmrg_heff_s {
   int64_t llen = 0, rlen = 0;
   double flops = 0.0, bytes = 0.0;
   int prec = DMRG_FP64;
-  dmrg::TuneTable tune;     // tile shape per (phase, size bucket)
+  dmrg::TuneTable tune[2];  // tile shape per (phase, size bucket), per precision
   int64_t work_budget = 0;  // doubles
   double* work = nullptr;
   int64_t work_elems = 0;
   double* part = nullptr;      // partials of cut long-K sums (forward)
+  int64_t part_elems = 0;      // its length (doubles), the larger of the two programs
   double* adj_part = nullptr;  // the same for the adjoint
-  dmrg::Program fwd;
+  // forward programs, one per precision (tile shapes differ); same waves,
+  // workspace offsets and summation order
+  dmrg::Program fwdp[2];
+  dmrg::Program& fwd() { return fwdp[prec == DMRG_SPLIT_BF16X3 ? 1 : 0]; }
   dmrg::Program adj;
   bool adj_built = false;
   int adj_mask = 0;

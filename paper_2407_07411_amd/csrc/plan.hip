@@ -48,6 +48,7 @@ int cfg_from_env() {
   if (v == 128) return CFG_F64_128;
   if (v == 1288) return CFG_F64_128W8;
   if (v == 256) return CFG_F64_256x128;
+  if (v == 64128) return CFG_F64_64x128;
   return -1;
 }
 
@@ -212,10 +213,11 @@ void opBt_as_z(const Item& it, bool* zt, int* ldz) {
 // contiguous ranges of the item list, which is in term order, so every wave
 // reaches most output blocks and its output sums span the whole of Y (many
 // tiles); long sums are cut into K parts by the builder.
-dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
+dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
-  pb.tune = &h->tune;
+  pb.split = which == 1;
+  pb.tune = &h->tune[which];
   const int nb = (int)h->blocks.size();
   const size_t ni = h->items.size();
   std::vector<uint8_t> lf_first(ni, 1), reached(nb, 0), written(nb, 0);
@@ -309,7 +311,7 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
     pb.phase_id = 1;
     pb.close_phase();
   }
-  h->fwd = std::move(pb.prog);
+  h->fwdp[which] = std::move(pb.prog);
   return DMRG_OK;
 }
 
@@ -322,7 +324,7 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override) {
 dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
-  pb.tune = &h->tune;
+  pb.tune = &h->tune[0];
   const int64_t nitems = (int64_t)h->items.size();
   std::vector<int64_t> woff(nitems, -1);
   int64_t budget = std::max<int64_t>(h->work_budget, 1);
@@ -514,7 +516,7 @@ Bases fwd_bases(dmrg_heff_s* h, const double* psi, double* y) {
 
 namespace dmrg {
 dmrg_status heff_apply_eager(dmrg_heff_s* h, const double* psi, double* y) {
-  return h->fwd.run(fwd_bases(h, psi, y), h->ctx->stream, h->prec);
+  return h->fwd().run(fwd_bases(h, psi, y), h->ctx->stream, h->prec);
 }
 }  // namespace dmrg
 
@@ -566,30 +568,39 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   if (st != DMRG_OK) return st;
   count_work(h.get());
   h->work_budget = workspace_budget_doubles();
-  if ((st = build_forward(h.get(), cfg_from_env())) != DMRG_OK) return st;
-  {
-    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0,
-                              h->fwd.part_elems};
-    if ((st = h->fwd.validate(len)) != DMRG_OK) return st;
+  int64_t part_elems = 0;
+  for (int which = 0; which < 2; ++which) {
+    if ((st = build_forward(h.get(), cfg_from_env(), which)) != DMRG_OK) return st;
+    part_elems = std::max(part_elems, h->fwdp[which].part_elems);
   }
-  if ((st = h->fwd.upload()) != DMRG_OK) return st;
-  if (!serial_from_env() && (st = h->fwd.prepare_concurrent()) != DMRG_OK) {
-    h->fwd.release();
+  for (int which = 0; which < 2; ++which) {
+    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0, part_elems};
+    if ((st = h->fwdp[which].validate(len)) != DMRG_OK) return st;
+  }
+  for (int which = 0; which < 2 && st == DMRG_OK; ++which) {
+    st = h->fwdp[which].upload();
+    if (st == DMRG_OK && !serial_from_env()) st = h->fwdp[which].prepare_concurrent();
+  }
+  if (st != DMRG_OK) {
+    for (auto& p : h->fwdp) p.release();
     return st;
   }
-  if (hipMalloc(&h->part, std::max<int64_t>(h->fwd.part_elems, 1) * sizeof(double)) != hipSuccess) {
+  h->part_elems = part_elems;
+  if (hipMalloc(&h->part, std::max<int64_t>(part_elems, 1) * sizeof(double)) != hipSuccess) {
     h->part = nullptr;
-    h->fwd.release();
+    for (auto& p : h->fwdp) p.release();
     return fail(DMRG_ENOMEM, "heff_create: partial-sum buffer allocation failed");
   }
   if (hipMalloc(&h->work, h->work_elems * sizeof(double)) != hipSuccess) {
     h->work = nullptr;
-    h->fwd.release();
+    for (auto& p : h->fwdp) p.release();
+    (void)hipFree(h->part);
     return fail(DMRG_ENOMEM, "heff_create: workspace allocation failed");
   }
   if ((st = build_diag(h.get())) != DMRG_OK) {
-    h->fwd.release();
+    for (auto& p : h->fwdp) p.release();
     (void)hipFree(h->work);
+    (void)hipFree(h->part);
     return st;
   }
   *out = h.release();
@@ -599,7 +610,7 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
 void dmrg_heff_destroy(dmrg_heff_t h) {
   if (!h) return;
   free_graph(h);
-  h->fwd.release();
+  for (auto& p : h->fwdp) p.release();
   h->adj.release();
   if (h->work) (void)hipFree(h->work);
   if (h->adj_work) (void)hipFree(h->adj_work);
@@ -667,7 +678,7 @@ dmrg_status dmrg_heff_apply(dmrg_heff_t h, const double* psi, double* y) {
 
 dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops) {
   if (!h || !n_launches) return fail(DMRG_EINVAL, "heff_launches: bad arguments");
-  const auto& P = h->fwd;
+  const auto& P = h->fwd();
   *n_launches = (int64_t)P.launches.size();
   for (size_t i = 0; i < P.launches.size(); ++i) {
     const Launch& l = P.launches[i];
@@ -693,7 +704,7 @@ dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kern
 dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y, float* ms) {
   if (!h || !psi || !y || !ms) return fail(DMRG_EINVAL, "heff_apply_profiled: bad arguments");
   hipStream_t s = h->ctx->stream;
-  const auto& P = h->fwd;
+  const auto& P = h->fwd();
   const size_t n = P.launches.size();
   std::vector<hipEvent_t> ev(n + 1, nullptr);
   dmrg_status st = DMRG_OK;
@@ -779,7 +790,8 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
 extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps) {
   if (!h || !psi || !y || reps < 1 || psi == y) return fail(DMRG_EINVAL, "heff_autotune: bad arguments");
   hipStream_t s = h->ctx->stream;
-  const Program& P = h->fwd;
+  const int which = h->prec == DMRG_SPLIT_BF16X3 ? 1 : 0;
+  const Program& P = h->fwdp[which];
   // problems of the current plan grouped by (phase, M bucket, N bucket)
   std::map<int, std::vector<int32_t>> groups;
   for (size_t pi = 0; pi < P.probs.size(); ++pi) {
@@ -849,21 +861,20 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
   }
   cleanup();
   // rebuild the forward program with the chosen shapes
-  h->tune = table;
-  Program old = std::move(h->fwd);
-  h->fwd = Program();
-  dmrg_status st = build_forward(h, -1);
-  if (st == DMRG_OK && h->fwd.part_elems > old.part_elems) st = fail(DMRG_EQN, "autotune: partials grew");
+  h->tune[which] = table;
+  Program old = std::move(h->fwdp[which]);
+  h->fwdp[which] = Program();
+  dmrg_status st = build_forward(h, -1, which);
+  if (st == DMRG_OK && h->fwdp[which].part_elems > h->part_elems) st = fail(DMRG_EQN, "autotune: partials grew");
   if (st == DMRG_OK) {
-    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0,
-                              std::max(h->fwd.part_elems, old.part_elems)};
-    st = h->fwd.validate(len);
+    int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0, h->part_elems};
+    st = h->fwdp[which].validate(len);
   }
-  if (st == DMRG_OK) st = h->fwd.upload();
-  if (st == DMRG_OK && !serial_from_env()) st = h->fwd.prepare_concurrent();
+  if (st == DMRG_OK) st = h->fwdp[which].upload();
+  if (st == DMRG_OK && !serial_from_env()) st = h->fwdp[which].prepare_concurrent();
   if (st != DMRG_OK) {
-    h->fwd.release();
-    h->fwd = std::move(old);
+    h->fwdp[which].release();
+    h->fwdp[which] = std::move(old);
     return st;
   }
   old.release();

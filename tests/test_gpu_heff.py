@@ -78,7 +78,7 @@ def test_matvec_l24_reduced_terms(ctx, l24):
     assert rel(y, ref) <= TOL
 
 
-@pytest.mark.parametrize("tile", ["32", "64", "128", "1288", "256"])
+@pytest.mark.parametrize("tile", ["32", "64", "128", "1288", "256", "64128"])
 def test_matvec_tile_shapes(ctx, l24, tile, monkeypatch):
     print("case tile", tile, flush=True)
     monkeypatch.setenv("DMRG_HEFF_TILE", tile)

@@ -30,7 +30,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("kind", ["tiny", "l24"])
-@pytest.mark.parametrize("tile", [None, "32", "64", "1288", "256"])
+@pytest.mark.parametrize("tile", [None, "32", "64", "1288", "256", "64128"])
 def test_split_matvec_bound(ctx, kind, tile, monkeypatch):
     from paper_2407_07411_amd.heff import SPLIT_BF16X3
     print("case", kind, tile, flush=True)
