@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the Davidson-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", action="store_true", help="run the tile-shape autotuner before timing")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the off-path measurements (SVD truncation, adjoint at L=24)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     return ap.parse_args()
@@ -222,6 +224,7 @@ def main():
         log(f"matvec split {sp_ms:.2f} ms -> {flops/sp_ms/1e9:.2f} TFLOPS (FP64-equivalent), rel err {sp_err:.2e}")
 
         # ---- Davidson to the 1e-6 residual from the lowest diagonal element
+        ground = None
         if not args.no_solve:
             for label, prec, tail in (("fp64", H.FP64, 0), ("split_fp64_tail", H.SPLIT_BF16X3, 40)):
                 h.set_precision(prec)
@@ -232,6 +235,8 @@ def main():
                 torch.cuda.synchronize()
                 r["seconds"] = round(time.perf_counter() - t0, 3)
                 extra["davidson_" + label] = r
+                if label == "fp64":
+                    ground = psi
                 log(f"davidson {label}:", r)
             h.set_precision(H.FP64)
             if extra["davidson_fp64"]["converged"] and extra["davidson_split_fp64_tail"]["converged"]:
@@ -239,6 +244,25 @@ def main():
                                                   - extra["davidson_split_fp64_tail"]["energy"])
                 extra["split_solve_speedup"] = round(extra["davidson_fp64"]["seconds"]
                                                      / extra["davidson_split_fp64_tail"]["seconds"], 3)
+
+        # ---- off the timed path, measured: SVD truncation of the FP64 ground state
+        if not args.no_extra:
+            torch.cuda.synchronize()
+            psi = ground if ground is not None else prob.psi
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                kept, U, S, Vt, terr = H.svd_truncate(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, psi,
+                                                      max_keep=w["D"])
+                torch.cuda.synchronize()
+                svd_s = time.perf_counter() - t0
+            extra["svd_truncate"] = dict(seconds=round(svd_s, 3), kept=int(np.sum(kept)), max_keep=w["D"],
+                                         trunc_err=terr,
+                                         state="FP64 ground state" if ground is not None else "random psi")
+            log(f"svd truncation: {svd_s:.3f} s, kept {int(np.sum(kept))}, error {terr:.3e}")
+            del U, S, Vt
+    if not args.no_extra:
+        extra["adjoint_l24_d1024"] = adjoint_timing(dev)
 
     cpu = None
     if not args.no_cpu:
@@ -257,6 +281,47 @@ def main():
                            step="one Davidson iteration incl. one H_eff matvec"),
                roofline=roofline, cpu_baseline=cpu, **extra)
     print(json.dumps(out), flush=True)
+
+
+def adjoint_timing(dev):
+    """Forward matvec and hand-written adjoint (psi-bar and both operator-pool
+    gradients, intermediates recomputed) on the L=24, D=1024 workload with
+    every operator pair, timed with HIP events on the library's stream."""
+    import torch
+
+    from paper_2407_07411_amd import heff as H
+    from synth.problem import WORKLOADS, make_problem
+    w = WORKLOADS["l24_d1024"]
+    prob = make_problem(w["L"], w["n_elec"], w["two_sz"], w["D"], w["seed"], device=dev)
+    stream = torch.cuda.Stream(dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(stream):
+        ctx = H.Context(0)
+        h = H.Heff(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, prob.terms, prob.left_pool,
+                   prob.right_pool)
+        flops, _ = h.flops()
+        x = prob.psi.clone()
+        y = torch.empty_like(x)
+        yb = torch.randn(x.numel(), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(3))
+        pb = torch.zeros_like(x)
+        lb = torch.zeros_like(prob.left_pool)
+        rb = torch.zeros_like(prob.right_pool)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for rep in range(2):  # the first pass builds the adjoint plan
+            ev[0].record(stream)
+            h.apply(x, y)
+            ev[1].record(stream)
+            h.adjoint(x, yb, pb, lb, rb)
+            ev[2].record(stream)
+        torch.cuda.synchronize()
+        fwd_ms = ev[0].elapsed_time(ev[1])
+        adj_ms = ev[1].elapsed_time(ev[2])
+    out = dict(terms=prob.meta["n_terms"], forward_ms=round(fwd_ms, 3),
+               forward_tflops=round(flops / fwd_ms / 1e9, 3), adjoint_ms=round(adj_ms, 3),
+               adjoint_over_forward=round(adj_ms / fwd_ms, 3),
+               adjoint_outputs="psi-bar, left-pool and right-pool gradients")
+    log("adjoint l24_d1024:", out)
+    return out
 
 
 def cpu_baseline(prob, target_s, lid, rid):

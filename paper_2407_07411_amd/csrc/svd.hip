@@ -4,9 +4,11 @@
 // (Introduction: "matrix factorization"; Numerical procedure: D sets the
 // accuracy).  With U(1)xU(1) symmetry the wavefunction is block diagonal in
 // the enlarged-left sector, so every block Psi[q, Q-q] is decomposed on its
-// own: one workgroup per block runs one-sided (Hestenes) Jacobi on the
-// block's columns (or on its transpose when it is wide), four wavefronts
-// rotating disjoint column pairs of a round-robin ordering at a time.  The
+// own by one-sided (Hestenes) Jacobi on the block's columns (or on its
+// transpose when it is wide).  Every launch is one round of a round-robin
+// ordering for all blocks together, one wavefront per disjoint column pair,
+// so the largest blocks are spread over the whole GPU; sweeps repeat until
+// no block rotates.  The
 // singular values of all blocks are then pooled and truncated on the host
 // (global top-D with a deterministic tie-break), and a pack kernel writes the
 // kept factors.
@@ -60,72 +62,90 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One-sided Jacobi: rotate column pairs of B until all are orthogonal to
-// relative tolerance tol; V accumulates the rotations.  Rotation of the
-// 2x2 Gram matrix [[alpha, gamma], [gamma, beta]] by the standard formulas.
-__global__ __launch_bounds__(256) void svd_jacobi_kernel(const SvdBlock* __restrict__ blocks,
-                                                         double* __restrict__ work,
-                                                         double* __restrict__ sigma, double tol,
-                                                         int max_sweeps) {
-  const SvdBlock b = blocks[blockIdx.x];
+// Column pair slot `pi` of round `rd` in the round-robin ordering of m (even)
+// columns: every round pairs all columns disjointly, m - 1 rounds visit every
+// pair once (a sweep).
+__device__ __forceinline__ void rr_pair(int pi, int rd, int m, int* p, int* q) {
+  int a = pi == 0 ? 0 : 1 + (pi - 1 + rd) % (m - 1);
+  const int pos = m - 1 - pi;
+  int b = pos == 0 ? 0 : 1 + (pos - 1 + rd) % (m - 1);
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+struct SvdPair {
+  int32_t blk, pi;  // block and pair slot
+};
+
+// One round of one-sided (Hestenes) Jacobi over every block at once: one
+// wavefront per column pair; the pairs of a round are disjoint, so the
+// rotations of a launch commute and the result does not depend on how waves
+// are scheduled.  A pair rotates when its columns are not orthogonal to
+// relative tolerance tol; V accumulates the rotations; flags[blk] records
+// that the block rotated in this sweep.  Rotation of the 2x2 Gram matrix
+// [[alpha, gamma], [gamma, beta]] by the standard formulas.
+__global__ __launch_bounds__(256) void svd_round_kernel(const SvdBlock* __restrict__ blocks,
+                                                        const SvdPair* __restrict__ pairs,
+                                                        int64_t npairs, int rd,
+                                                        double* __restrict__ work,
+                                                        int32_t* __restrict__ flags, double tol) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (wid >= npairs) return;
+  const SvdPair pr = pairs[wid];
+  const SvdBlock b = blocks[pr.blk];
+  const int r = b.r, c = b.c;
+  const int m = c + (c & 1);
+  if (c < 2 || rd >= m - 1) return;
+  int p, q;
+  rr_pair(pr.pi, rd, m, &p, &q);
+  if (q >= c) return;  // bye
   double* B = work + b.boff;
   double* V = work + b.voff;
+  double* bp = B + (int64_t)p * r;
+  double* bq = B + (int64_t)q * r;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = lane; i < r; i += 64) {
+    const double x = bp[i], y = bq[i];
+    al += x * x;
+    be += y * y;
+    ga += x * y;
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  if (!(fabs(ga) > tol * sqrt(al * be)) || ga == 0.0) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+  for (int i = lane; i < r; i += 64) {
+    const double x = bp[i], y = bq[i];
+    bp[i] = cs * x - sn * y;
+    bq[i] = sn * x + cs * y;
+  }
+  double* vp = V + (int64_t)p * c;
+  double* vq = V + (int64_t)q * c;
+  for (int i = lane; i < c; i += 64) {
+    const double x = vp[i], y = vq[i];
+    vp[i] = cs * x - sn * y;
+    vq[i] = sn * x + cs * y;
+  }
+  if (lane == 0) flags[pr.blk] = 1;
+}
+
+__global__ void svd_clear_kernel(int32_t* __restrict__ flags, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) flags[i] = 0;
+}
+
+// Singular values = column norms of the converged B; its columns, normalised,
+// are the singular vectors on B's side.
+__global__ __launch_bounds__(256) void svd_finish_kernel(const SvdBlock* __restrict__ blocks,
+                                                         double* __restrict__ work,
+                                                         double* __restrict__ sigma) {
+  const SvdBlock b = blocks[blockIdx.x];
+  double* B = work + b.boff;
   const int r = b.r, c = b.c;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  __shared__ int rotated;
-  const int m = c + (c & 1);
-  for (int sweep = 0; sweep < max_sweeps && c > 1; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
-    for (int rd = 0; rd < m - 1; ++rd) {
-      for (int pi = wave; pi < m / 2; pi += nwaves) {
-        int p = pi == 0 ? 0 : 1 + (pi - 1 + rd) % (m - 1);
-        const int pos = m - 1 - pi;
-        int q = pos == 0 ? 0 : 1 + (pos - 1 + rd) % (m - 1);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        if (q >= c) continue;  // bye
-        double* bp = B + (int64_t)p * r;
-        double* bq = B + (int64_t)q * r;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < r; i += 64) {
-          const double x = bp[i], y = bq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (!(fabs(ga) > tol * sqrt(al * be)) || ga == 0.0) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = lane; i < r; i += 64) {
-          const double x = bp[i], y = bq[i];
-          bp[i] = cs * x - sn * y;
-          bq[i] = sn * x + cs * y;
-        }
-        double* vp = V + (int64_t)p * c;
-        double* vq = V + (int64_t)q * c;
-        for (int i = lane; i < c; i += 64) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = cs * x - sn * y;
-          vq[i] = sn * x + cs * y;
-        }
-        if (lane == 0) rotated = 1;
-      }
-      __syncthreads();
-    }
-    const int any = rotated;
-    __syncthreads();  // every thread has read the flag before it is reset
-    if (!any) break;
-  }
-  __syncthreads();
-  // singular values = column norms; normalise the columns (left vectors)
   for (int j = wave; j < c; j += nwaves) {
     double* bj = B + (int64_t)j * r;
     double s2 = 0.0;
@@ -226,12 +246,48 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
     return fail(DMRG_ENOMEM, "svd_truncate: device allocation failed");
   }
   std::vector<double> sig(soff);
+  // flattened (block, pair slot) list; rounds per sweep = the largest block's
+  std::vector<SvdPair> pairs;
+  int max_rounds = 0;
+  for (int i = 0; i < nb; ++i) {
+    const int c = blocks[i].c, m = c + (c & 1);
+    if (c < 2) continue;
+    for (int pi = 0; pi < m / 2; ++pi) pairs.push_back(SvdPair{i, pi});
+    max_rounds = std::max(max_rounds, m - 1);
+  }
+  SvdPair* dpairs = nullptr;
+  int32_t* dflags = nullptr;
+  if (hipMalloc(&dpairs, std::max<size_t>(pairs.size(), 1) * sizeof(SvdPair)) != hipSuccess ||
+      hipMalloc(&dflags, nb * sizeof(int32_t)) != hipSuccess) {
+    if (dpairs) (void)hipFree(dpairs);
+    cleanup();
+    return fail(DMRG_ENOMEM, "svd_truncate: device allocation failed");
+  }
   hipError_t e = hipMemcpyAsync(dblocks, blocks.data(), nb * sizeof(SvdBlock), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !pairs.empty())
+    e = hipMemcpyAsync(dpairs, pairs.data(), pairs.size() * sizeof(SvdPair), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     svd_load_kernel<<<nb, 256, 0, s>>>(dblocks, psi, work);
-    svd_jacobi_kernel<<<nb, 256, 0, s>>>(dblocks, work, dsig, 1e-15, 60);
     e = hipGetLastError();
   }
+  const int64_t npairs = (int64_t)pairs.size();
+  const unsigned grid = (unsigned)std::max<int64_t>(1, (npairs + 3) / 4);
+  std::vector<int32_t> flags(nb, 0);
+  for (int sweep = 0; sweep < 60 && npairs > 0 && e == hipSuccess; ++sweep) {
+    svd_clear_kernel<<<1, 256, 0, s>>>(dflags, nb);
+    for (int rd = 0; rd < max_rounds; ++rd)
+      svd_round_kernel<<<grid, 256, 0, s>>>(dblocks, dpairs, npairs, rd, work, dflags, 1e-15);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), dflags, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && std::all_of(flags.begin(), flags.end(), [](int32_t f) { return f == 0; })) break;
+  }
+  if (e == hipSuccess) {
+    svd_finish_kernel<<<nb, 256, 0, s>>>(dblocks, work, dsig);
+    e = hipGetLastError();
+  }
+  (void)hipFree(dpairs);
+  (void)hipFree(dflags);
   if (e == hipSuccess) e = hipMemcpyAsync(sig.data(), dsig, soff * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
