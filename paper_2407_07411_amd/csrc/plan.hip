@@ -368,6 +368,7 @@ dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
                                it.alpha));
       }
     }
+    pb.phase_id = 0;
     pb.close_phase();
     // phase 2: psibar blocks, left-pool blocks, right-pool blocks
     std::map<int32_t, std::vector<int64_t>> by_in;
@@ -453,6 +454,7 @@ dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
         }
       }
     }
+    pb.phase_id = 1;
     pb.close_phase();
     i0 = i1;
   }
@@ -764,6 +766,10 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
       return fail(DMRG_ENOMEM, "heff_apply_adjoint: partial-sum buffer allocation failed");
     }
     if ((st = h->adj.upload()) != DMRG_OK) return st;
+    if (!serial_from_env() && (st = h->adj.prepare_concurrent()) != DMRG_OK) {
+      h->adj.release();
+      return st;
+    }
     if (hipMalloc(&h->adj_work, h->adj_work_elems * sizeof(double)) != hipSuccess) {
       h->adj_work = nullptr;
       h->adj.release();
