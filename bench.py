@@ -31,7 +31,7 @@ KERNEL_NAMES = {0: "gemm_f64_kernel<32,32,16,1,1>", 1: "gemm_f64_kernel<64,64,16
                 4: "gemm_f64_kernel<256,128,16,4,2>", 5: "gemm_f64_kernel<64,128,16,2,4>",
                 16: "gemm_split_kernel<32,32,1,1>",
                 17: "gemm_split_kernel<64,64,2,2>", 18: "gemm_split_kernel<128,128,2,2>",
-                19: "gemm_split_kernel<128,128,4,2>", 20: "gemm_split_kernel<256,128,4,4>",
+                19: "gemm_split_kernel<128,128,4,4,1,64>", 20: "gemm_split_kernel<256,128,4,4>",
                 21: "gemm_split_kernel<64,128,2,4>",
                 32: "reduce_kernel"}
 

@@ -8,21 +8,22 @@
 // product of two split values keeps the six slice products with i + j <= 2
 // (the dropped ones are O(2^-24) relative).  Slice products are exact in FP32;
 // the matrix cores sum them in FP32, and at the end of every segment and every
-// SPLIT_FLUSH K tiles the FP32 partial, times the segment's alpha, is added
-// into an FP64 accumulator, which bounds FP32 rounding to SPLIT_FLUSH * 32 K
+// SPLIT_FLUSH_K values of K the FP32 partial, times the segment's alpha, is
+// added into an FP64 accumulator, which bounds FP32 rounding to SPLIT_FLUSH_K K
 // values.  The problem/segment/tile tables and the output-stationary ordering
 // are those of the FP64 kernel, so results are deterministic.
 //
 // Staging: a thread owns groups of 8 K values of one operand row (one row of X
-// or one column of Z).  Group kg of a row holds k = k0 + kg + 4e, e = 0..7, at
-// LDS positions 8kg + e; X and Z use the same K permutation, so the products
-// are unchanged.  Where the operand is contiguous in K, four neighbouring
-// lanes read one 32-byte run per load; where it is contiguous in the row
-// index, neighbouring lanes read neighbouring rows.  The eight values are
-// converted pairwise (v_cvt_pk_bf16_f32) and each slice lands in LDS as one
-// 16-byte store.  LDS is double-buffered where it fits: the split and store of
-// the next K tile run while the matrix cores work on the current one, and one
-// barrier separates K tiles.
+// or one column of Z).  With KG = BK/8 groups per row and K tile, group kg
+// holds k = k0 + kg + KG e, e = 0..7, at LDS positions 8kg + e; X and Z use
+// the same K permutation, so the products are unchanged.  Where the operand
+// is contiguous in K, KG neighbouring lanes read one run of KG doubles per
+// load; where it is contiguous in the row index, neighbouring lanes read
+// neighbouring rows.  The eight values are converted pairwise
+// (v_cvt_pk_bf16_f32) and each slice lands in LDS as one 16-byte store.  With
+// two LDS buffers the split and store of the next K tile run while the matrix
+// cores work on the current one and one barrier separates K tiles; with one
+// buffer (deeper K tiles) two barriers do.
 //
 // Matrix core: v_mfma_f32_32x32x16_bf16.  Lanes: A[i][k] holds i = l%32,
 // k = 8(l/32) + e; B[k][j] holds j = l%32, k = 8(l/32) + e (e = 0..7); the 16
@@ -37,10 +38,8 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 
-constexpr int SPLIT_BK = 32;
-constexpr int SPLIT_KG = SPLIT_BK / 8;  // 8-value groups per row and K tile
-constexpr int SPLIT_LDK = SPLIT_BK + 8; // LDS row length (bf16), 80 bytes
-constexpr int SPLIT_FLUSH = 4;          // K tiles per FP32 partial
+constexpr int SPLIT_BK = 32;            // default K tile depth
+constexpr int SPLIT_FLUSH_K = 128;      // K values per FP32 partial
 
 __device__ __forceinline__ int64_t xcd_remap_s(int64_t bid, int64_t n) {
   const int64_t per = n / 8, rem = n % 8;
@@ -67,16 +66,18 @@ __device__ __forceinline__ void split_pair(double a, double b, uint32_t& s0, uin
 constexpr uint32_t OOB_S = 0xffffffffu;
 
 // The 8-value groups of one operand (ROWS x BK per K tile) that a thread
-// stages: up to G groups, group r is gi = tid + r * NT < ROWS * SPLIT_KG.
+// stages: up to G groups, group r is gi = tid + r * NT < ROWS * KG.
 // Loads go through a buffer resource whose scalar base walks K; per-lane
 // offsets are fixed for a segment and the step between the 8 values of a group
 // is a scalar offset, so full K tiles cost no vector address arithmetic.  Rows
 // outside the problem are clamped to its last row: they feed only outputs
 // that are never stored.  In the K tail, offsets at or beyond num_records
 // read as zero (with no scalar offset added).
-template <int ROWS, int NT>
+template <int ROWS, int NT, int BK>
 struct Stager {
-  static constexpr int NG = ROWS * SPLIT_KG;
+  static constexpr int KG = BK / 8;       // 8-value groups per row and K tile
+  static constexpr int LDK = BK + 8;      // LDS row length (bf16)
+  static constexpr int NG = ROWS * KG;
   static constexpr int G = (NG + NT - 1) / NT;
   static constexpr bool EXACT = NG % NT == 0;
   static_assert(EXACT || G == 1, "staging shape");
@@ -92,13 +93,13 @@ struct Stager {
   __device__ __forceinline__ void setup(const double* seg, int ld, bool kc, int r0, int nrows,
                                         int tid) {
     base = kc ? seg + (int64_t)r0 * ld : seg + r0;
-    tstep = kc ? (int64_t)SPLIT_BK : (int64_t)SPLIT_BK * ld;
-    estep = kc ? 8u * SPLIT_KG : 8u * SPLIT_KG * (uint32_t)ld;
+    tstep = kc ? (int64_t)BK : (int64_t)BK * ld;
+    estep = kc ? 8u * KG : 8u * KG * (uint32_t)ld;
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const int gi = EXACT ? tid + r * NT : min(tid, NG - 1);
-      row[r] = kc ? gi / SPLIT_KG : gi % ROWS;
-      kg[r] = kc ? gi % SPLIT_KG : gi / ROWS;
+      row[r] = kc ? gi / KG : gi % ROWS;
+      kg[r] = kc ? gi % KG : gi / ROWS;
       const int rc = min(row[r], nrows - 1 - r0);
       off[r] = kc ? (uint32_t)(rc * ld + kg[r]) * 8u : (uint32_t)(kg[r] * ld + rc) * 8u;
     }
@@ -108,7 +109,7 @@ struct Stager {
   __device__ __forceinline__ void load(int kleft) {
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, 0x7fffffff, 0x00020000);
-    if (kleft >= SPLIT_BK) {
+    if (kleft >= BK) {
 #pragma unroll
       for (int r = 0; r < G; ++r)
 #pragma unroll
@@ -119,7 +120,7 @@ struct Stager {
       for (int r = 0; r < G; ++r)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const uint32_t o = kg[r] + SPLIT_KG * e < kleft ? off[r] + e * estep : OOB_S;
+          const uint32_t o = kg[r] + KG * e < kleft ? off[r] + e * estep : OOB_S;
           v[r][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0));
         }
     }
@@ -127,8 +128,8 @@ struct Stager {
 
   __device__ __forceinline__ void advance() { base += tstep; }
 
-  // Split and store into the three slice planes sh[sl][ROWS][SPLIT_LDK].
-  __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][SPLIT_LDK], int tid) {
+  // Split and store into the three slice planes sh[sl][ROWS][LDK].
+  __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][LDK], int tid) {
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       if (!EXACT && tid >= NG) continue;
@@ -145,22 +146,25 @@ struct Stager {
   }
 };
 
-template <int BM, int BN>
+template <int BM, int BN, int BK>
 constexpr int split_nbuf() {
-  return 2 * 3 * (BM + BN) * SPLIT_LDK * 2 <= 160 * 1024 ? 2 : 1;
+  return 2 * 3 * (BM + BN) * (BK + 8) * 2 <= 160 * 1024 ? 2 : 1;
 }
 
-template <int BM, int BN, int WGM, int WGN>
+// NBUF: LDS buffers (0: two where they fit, else one); BK: K tile depth.
+template <int BM, int BN, int WGM, int WGN, int NBUF = 0, int BK = SPLIT_BK>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
     Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
     const Tile* __restrict__ tiles, int64_t ntiles) {
   constexpr int NT = 64 * WGM * WGN;
-  constexpr int NB = split_nbuf<BM, BN>();
+  constexpr int NB = NBUF > 0 ? NBUF : split_nbuf<BM, BN, BK>();
+  constexpr int LDK = BK + 8;
+  constexpr int FLUSH = SPLIT_FLUSH_K / BK > 0 ? SPLIT_FLUSH_K / BK : 1;  // K tiles per FP32 partial
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 32, FN = WN / 32;
   static_assert(FM >= 1 && FN >= 1, "tile shape");
-  __shared__ __attribute__((aligned(16))) __bf16 Xh[NB][3][BM][SPLIT_LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Zh[NB][3][BN][SPLIT_LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Xh[NB][3][BM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Zh[NB][3][BN][LDK];
 
   const int64_t lt = xcd_remap_s(blockIdx.x, ntiles);
   const Tile t = tiles[lt];
@@ -193,8 +197,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
 
   const int s_end = p.seg0 + p.nseg;
   if (p.nseg > 0) {
-    Stager<BM, NT> xs;
-    Stager<BN, NT> zs;
+    Stager<BM, NT, BK> xs;
+    Stager<BN, NT, BK> zs;
     int s = p.seg0, k0 = 0, since_flush = 0, buf = 0;
     Seg g = segs[s];
     xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
     __syncthreads();
     while (true) {
       // next (segment, K tile) position; its global loads go out first
-      int s2 = s, k2 = k0 + SPLIT_BK;
+      int s2 = s, k2 = k0 + BK;
       Seg g2 = g;
       if (k2 >= g.K) {
         ++s2;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
       }
       const int cb = NB == 2 ? buf : 0;
 #pragma unroll
-      for (int kk = 0; kk < (active ? SPLIT_BK : 0); kk += 16) {
+      for (int kk = 0; kk < (active ? BK : 0); kk += 16) {
         bf8 a[3][FM], b[3][FN];
 #pragma unroll
         for (int sl = 0; sl < 3; ++sl) {
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
         xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid);
         zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid);
       }
-      if (++since_flush == SPLIT_FLUSH || seg_end) {
+      if (++since_flush == FLUSH || seg_end) {
         since_flush = 0;
         const double al = g.alpha;
 #pragma unroll
@@ -309,8 +313,8 @@ dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs
     case CFG_F64_128:
       gemm_split_kernel<128, 128, 2, 2><<<grid, 256, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
-    case CFG_F64_128W8:
-      gemm_split_kernel<128, 128, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+    case CFG_F64_128W8:  // sixteen 32x32 waves, 64-deep K tiles in one LDS buffer (measured fastest)
+      gemm_split_kernel<128, 128, 4, 4, 1, 64><<<grid, 1024, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
     case CFG_F64_64x128:
       gemm_split_kernel<64, 128, 2, 4><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
