@@ -128,11 +128,23 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
   const Prob p = probs[t.prob];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // Output sub-tile of this wave, rotated by block so that the waves an edge
-  // tile leaves idle fall on different SIMDs from block to block.
+  // Output sub-tile of this wave.  Waves are dealt to the four SIMDs in turn
+  // (wave w on SIMD w % 4).  For 2 x 4 wave grids the two waves of a SIMD take
+  // columns s and s + 2 of different rows, so that an edge tile whose last one
+  // or two wave columns (or last wave row) hold no output leaves at most one
+  // busy wave per SIMD; the SIMD order rotates by block.  Other grids rotate
+  // the row-major order by block.
   constexpr int NW = WGM * WGN;
-  const int role = (wave + 2 * (int)(blockIdx.x & 3)) % NW;
-  const int wm = role / WGN, wn = role % WGN;
+  int wm, wn;
+  if (WGM == 2 && WGN == 4) {
+    const int simd = (wave + (int)(blockIdx.x & 3)) & 3, slot = wave >> 2;
+    wm = slot;
+    wn = slot == 0 ? simd : (simd + 2) & 3;
+  } else {
+    const int role = (wave + 2 * (int)(blockIdx.x & 3)) % NW;
+    wm = role / WGN;
+    wn = role % WGN;
+  }
   const int m0 = t.tm * BM, n0 = t.tn * BN;
   const int fr = lane & 15, fk = lane >> 4;
   const bool active = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
