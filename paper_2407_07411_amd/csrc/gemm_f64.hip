@@ -10,9 +10,9 @@
 // order by one workgroup: no atomics, bit-reproducible results.
 //
 // Pipelining: the (segment, K tile) sequence of a tile is walked as one flat
-// stream; the global loads of the next K tile are issued into registers
-// before the matrix-core work on the current LDS buffer, and land in the other
-// LDS buffer afterwards, so one barrier separates consecutive K tiles.
+// stream; after the matrix-core work on the current LDS buffer is issued, the
+// global loads of the next K tile go out and land in the other LDS buffer, so
+// one barrier separates consecutive K tiles.
 //
 // Matrix core: v_mfma_f64_16x16x4_f64.  Operand lanes: A[i][k] comes from lane
 // i + 16k, B[k][j] from lane j + 16k; the four result doubles of lane l hold
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
     __syncthreads();
     int buf = 0;
     while (true) {
-      // next (segment, K tile) position; its global loads go out first
+      // next (segment, K tile) position
       int s2 = s, k2 = k0 + BK;
       Seg g2 = g;
       if (k2 >= g.K) {
@@ -185,10 +185,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
       } else {
         xs.advance();
         zs.advance();
-      }
-      if (more) {
-        xs.load(g2.K - k2);
-        zs.load(g2.K - k2);
       }
       // edge tiles: a wave whose output rows or columns all lie outside the
       // problem issues no LDS reads or MFMAs
@@ -208,7 +204,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
         }
       }
       if (!more) break;
-      // the other buffer was last read before the previous barrier
+      // Loads of the next K tile go out after this tile's MFMAs are issued
+      // (measured faster than before them: the matrix-core work of the other
+      // waves on the SIMD covers their latency).  The other LDS buffer was
+      // last read before the previous barrier.
+      xs.load(g2.K - k2);
+      zs.load(g2.K - k2);
       xs.store(&Xs[buf ^ 1][0][0], g2.alpha);
       zs.store(&Zs[buf ^ 1][0][0], 1.0);
       __syncthreads();
