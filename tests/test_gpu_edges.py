@@ -1,0 +1,100 @@
+"""Edge cases of the matvec path on the GPU: no terms at all (H_eff = 0),
+terms whose blocks are all absent, 1 x 1 wavefunction blocks, one-sided terms
+only, and operator offsets that break the pools or the selection rules
+(rejected on the host when the plan is built, before any launch)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.heff import heff_apply, heff_diag
+from synth.problem import Problem, Term
+from tests.conftest import tiny_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2407_07411_amd.heff import Context
+    return Context(0)
+
+
+def _heff(ctx, prob, prec=0):
+    from paper_2407_07411_amd.heff import Heff
+    return Heff(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, prob.terms, prob.left_pool.to("cuda"),
+                prob.right_pool.to("cuda"), prec=prec)
+
+
+def _with_terms(prob, terms):
+    return Problem(prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, terms, prob.left_pool, prob.right_pool, prob.psi)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_no_terms_gives_zero(ctx, prec):
+    print("case no terms", prec, flush=True)
+    prob = _with_terms(tiny_problem(seed=3), [])
+    h = _heff(ctx, prob, prec)
+    y = torch.full_like(prob.psi, 7.0).cuda()
+    h.apply(prob.psi.cuda(), y)
+    assert torch.count_nonzero(y).item() == 0
+    d = torch.full_like(y, 3.0)
+    h.diag(d)
+    assert torch.count_nonzero(d).item() == 0
+
+
+def test_terms_without_blocks_contribute_nothing(ctx):
+    print("case absent blocks", flush=True)
+    prob = tiny_problem(seed=5)
+    empty = []
+    for t in prob.terms:
+        lo = None if t.left_off is None else np.full_like(t.left_off, -1)
+        ro = None if t.right_off is None else np.full_like(t.right_off, -1)
+        empty.append(Term(dq=t.dq, odd=t.odd, hc=t.hc, one_sided=t.one_sided, coeff=t.coeff,
+                          left_off=lo, right_off=ro))
+    keep = prob.terms[:3]
+    p2 = _with_terms(prob, empty + keep)
+    h = _heff(ctx, p2)
+    y = h.apply(p2.psi.cuda()).cpu().numpy()
+    ref = heff_apply(_with_terms(prob, keep))
+    assert np.linalg.norm(y - ref) <= 1e-12 * max(np.linalg.norm(ref), 1e-300)
+
+
+def test_unit_blocks_and_one_sided_only(ctx):
+    """Sectors of dimension 1 (every GEMM is 1 x 1 x 1) and a term list of
+    one-sided (H_L, H_R) pairs only."""
+    print("case unit blocks", flush=True)
+    prob = tiny_problem(seed=7, D=2)
+    assert int(np.min(prob.Ld)) == 1
+    one = [t for t in prob.terms if t.one_sided]
+    for terms in (prob.terms, one):
+        p2 = _with_terms(prob, terms)
+        h = _heff(ctx, p2)
+        y = h.apply(p2.psi.cuda()).cpu().numpy()
+        ref = heff_apply(p2)
+        assert np.linalg.norm(y - ref) <= 1e-12 * max(np.linalg.norm(ref), 1e-300)
+        d = torch.zeros_like(p2.psi).cuda()
+        h.diag(d)
+        assert np.abs(d.cpu().numpy() - heff_diag(p2)).max() <= 1e-13 * max(1.0, np.abs(heff_diag(p2)).max())
+
+
+def test_invalid_offsets_rejected_on_host(ctx):
+    """A block offset that runs past its pool, or a term whose shift leaves
+    the sector basis, is refused by heff_create (no launch happens)."""
+    from paper_2407_07411_amd._lib import DmrgError
+    DMRG_EQN = -2
+    print("case invalid offsets", flush=True)
+    prob = tiny_problem(seed=9)
+    two = [t for t in prob.terms if not t.one_sided][0]
+    lo = two.left_off.copy()
+    a = int(np.nonzero(lo >= 0)[0][0])
+    lo[a] = prob.left_pool.numel() - 1  # the block cannot fit
+    bad = Term(dq=two.dq, odd=two.odd, hc=two.hc, one_sided=0, coeff=two.coeff, left_off=lo,
+               right_off=two.right_off)
+    with pytest.raises(DmrgError) as e:
+        _heff(ctx, _with_terms(prob, [bad]))
+    assert e.value.status == DMRG_EQN
+    far = Term(dq=(40, 0), odd=0, hc=0, one_sided=0, coeff=1.0, left_off=two.left_off,
+               right_off=two.right_off)
+    with pytest.raises(DmrgError) as e:
+        _heff(ctx, _with_terms(prob, [far]))
+    assert e.value.status == DMRG_EQN
