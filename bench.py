@@ -101,7 +101,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term-sharded "
-              "multi-GPU layout is a design note, not part of this build", file=sys.stderr)
+              "multi-GPU layout is described in the design notes, not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -49,7 +49,7 @@ typedef enum {
   DMRG_ENOMEM = -3,   /* device or host allocation failed                      */
   DMRG_EHIP = -4,     /* a HIP runtime call or kernel launch failed            */
   DMRG_ENOCONV = -5,  /* Davidson stopped before reaching the tolerance        */
-  DMRG_ENOTSUP = -6   /* combination not supported by this build               */
+  DMRG_ENOTSUP = -6   /* combination not supported by this library             */
 } dmrg_status;
 
 /* Arithmetic of the sector GEMMs.  Everything else (Davidson
