@@ -7,7 +7,7 @@ iteration (Rayleigh-Ritz, residual, preconditioner, Gram-Schmidt and one
 H_eff matvec), all on the device in FP64.  `value` is the algorithmic FP64
 FLOP rate of the matvecs over the timed steps (wall clock of whole steps).
 
-Also reported: the matvec alone (FP64 and split BF16x3), the roofline of the
+Also reported: the matvec alone (FP64, split BF16x3, FP32 operands), the roofline of the
 dominant kernel from per-launch HIP events, Davidson to a 1e-6 residual, and
 the CPU FP64 oracle timed on a bounded sample of the same workload.
 
@@ -33,7 +33,10 @@ KERNEL_NAMES = {0: "gemm_f64_kernel<32,32,16,1,1>", 1: "gemm_f64_kernel<64,64,16
                 17: "gemm_split_kernel<64,64,2,2>", 18: "gemm_split_kernel<128,128,2,2>",
                 19: "gemm_split_kernel<128,128,4,4,1,64>", 20: "gemm_split_kernel<256,128,4,4>",
                 21: "gemm_split_kernel<64,128,2,4>",
-                32: "reduce_kernel"}
+                32: "reduce_kernel",
+                48: "gemm_f32_kernel<32,32,32,1,1>", 49: "gemm_f32_kernel<64,64,32,2,2>",
+                50: "gemm_f32_kernel<128,128,16,2,2>", 51: "gemm_f32_kernel<128,128,32,4,2>",
+                52: "gemm_f32_kernel<256,128,16,4,2>", 53: "gemm_f32_kernel<64,128,32,2,4>"}
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -218,15 +221,30 @@ def main():
         torch.cuda.synchronize()
         sp_ms = ev[0].elapsed_time(ev[1]) / reps
         sp_err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
-        h.set_precision(H.FP64)
         extra.update(matvec_ms_split=round(sp_ms, 3), matvec_tflops_split=round(flops / sp_ms / 1e9, 3),
                      split_speedup=round(mv_ms / sp_ms, 3), split_matvec_rel_err=sp_err)
         log(f"matvec split {sp_ms:.2f} ms -> {flops/sp_ms/1e9:.2f} TFLOPS (FP64-equivalent), rel err {sp_err:.2e}")
 
+        # ---- FP32 operands on the FP32 matrix cores: matvec rate and error
+        h.set_precision(H.FP32)
+        h.apply(x, y)
+        ev[0].record(stream)
+        for _ in range(reps):
+            h.apply(x, y)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        f32_ms = ev[0].elapsed_time(ev[1]) / reps
+        f32_err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
+        h.set_precision(H.FP64)
+        extra.update(matvec_ms_fp32=round(f32_ms, 3), matvec_tflops_fp32=round(flops / f32_ms / 1e9, 3),
+                     fp32_speedup=round(mv_ms / f32_ms, 3), fp32_matvec_rel_err=f32_err)
+        log(f"matvec fp32 {f32_ms:.2f} ms -> {flops/f32_ms/1e9:.2f} TFLOPS (FP64-equivalent), rel err {f32_err:.2e}")
+
         # ---- Davidson to the 1e-6 residual from the lowest diagonal element
         ground = None
         if not args.no_solve:
-            for label, prec, tail in (("fp64", H.FP64, 0), ("split_fp64_tail", H.SPLIT_BF16X3, 40)):
+            for label, prec, tail in (("fp64", H.FP64, 0), ("split_fp64_tail", H.SPLIT_BF16X3, 40),
+                                      ("fp32_fp64_tail", H.FP32, 40)):
                 h.set_precision(prec)
                 psi = prob.psi.clone()
                 torch.cuda.synchronize()
@@ -239,11 +257,11 @@ def main():
                     ground = psi
                 log(f"davidson {label}:", r)
             h.set_precision(H.FP64)
-            if extra["davidson_fp64"]["converged"] and extra["davidson_split_fp64_tail"]["converged"]:
-                extra["split_energy_error"] = abs(extra["davidson_fp64"]["energy"]
-                                                  - extra["davidson_split_fp64_tail"]["energy"])
-                extra["split_solve_speedup"] = round(extra["davidson_fp64"]["seconds"]
-                                                     / extra["davidson_split_fp64_tail"]["seconds"], 3)
+            for lab in ("split", "fp32"):
+                r = extra[f"davidson_{lab}_fp64_tail"]
+                if extra["davidson_fp64"]["converged"] and r["converged"]:
+                    extra[f"{lab}_energy_error"] = abs(extra["davidson_fp64"]["energy"] - r["energy"])
+                    extra[f"{lab}_solve_speedup"] = round(extra["davidson_fp64"]["seconds"] / r["seconds"], 3)
 
         # ---- off the timed path, measured: SVD truncation of the FP64 ground state
         if not args.no_extra:

@@ -56,9 +56,12 @@ typedef enum {
  * orthogonalisation, Rayleigh quotient, residuals, SVD) is always FP64. */
 typedef enum {
   DMRG_FP64 = 0,          /* FP64 MFMA (v_mfma_f64_16x16x4)                    */
-  DMRG_SPLIT_BF16X3 = 1   /* operands split into 3 BF16 slices, products of    */
+  DMRG_SPLIT_BF16X3 = 1,  /* operands split into 3 BF16 slices, products of    */
                           /* slice pairs i+j<=2 on BF16 MFMA with FP32          */
                           /* accumulation per K chunk, FP64 combine             */
+  DMRG_FP32 = 3           /* operands rounded to FP32, FP32 MFMA               */
+                          /* (v_mfma_f32_16x16x4f32), FP32 accumulation per K   */
+                          /* chunk, FP64 combine.  Value 2 is not used.        */
 } dmrg_prec;
 
 typedef struct dmrg_ctx_s* dmrg_ctx_t;      /* device + borrowed HIP stream      */
@@ -182,8 +185,9 @@ typedef struct {
   int32_t restart_keep;  /* Ritz vectors kept at restart, 1..max_subspace-1  */
   int32_t use_graph;     /* 1: replay each iteration as one hipGraph         */
   double tol;            /* stop when ||H x - theta x||_2 <= tol, ||x|| = 1  */
-  int32_t fp64_tail;     /* split precision: iterations run in FP64 after the */
-                         /* split-precision phase stalls (0 = none)           */
+  int32_t fp64_tail;     /* reduced precision (split or FP32): iterations run */
+                         /* in FP64 after the reduced phase reaches its own   */
+                         /* error level (0 = none)                            */
   int32_t start;         /* 0: start from the given vector; 1: from the unit  */
                          /* vector at the lowest diagonal element (lowest     */
                          /* index on ties), the given vector is ignored       */

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdmrg_hef
 DMRG_OK = 0
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_EQN", -3: "DMRG_ENOMEM", -4: "DMRG_EHIP",
           -5: "DMRG_ENOCONV", -6: "DMRG_ENOTSUP"}
-FP64, SPLIT_BF16X3 = 0, 1
+FP64, SPLIT_BF16X3, FP32 = 0, 1, 3
 
 
 class Term(ctypes.Structure):

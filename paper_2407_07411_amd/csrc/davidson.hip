@@ -710,9 +710,9 @@ dmrg_status solve(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts, d
 }
 
 
-// The split matvec's own error on a generic vector, ||(H_split - H) u|| for
-// u = psi / ||psi||: the level below which split-precision residuals stop
-// meaning anything.  Costs one FP64 and one split matvec.
+// The reduced-precision matvec's own error on a generic vector,
+// ||(H_reduced - H) u|| for u = psi / ||psi||: the level below which its
+// residuals stop meaning anything.  Costs one FP64 and one reduced matvec.
 dmrg_status split_floor(dmrg_heff_t h, const double* psi, double* delta) {
   const int64_t n = dmrg_heff_size(h);
   if (n <= 0) return fail(DMRG_EINVAL, "davidson: empty wavefunction");
@@ -722,12 +722,11 @@ dmrg_status split_floor(dmrg_heff_t h, const double* psi, double* delta) {
   const int64_t len = 2 * n + (int64_t)RED_BLOCKS * KMAX + 2;
   if (hipMalloc(&mem, len * sizeof(double)) != hipSuccess) return fail(DMRG_ENOMEM, "davidson: allocation failed");
   double *y64 = mem, *ys = mem + n, *partial = mem + 2 * n, *out = partial + (int64_t)RED_BLOCKS * KMAX;
-  const int keep = h->prec;
+  const int keep = h->prec;  // the reduced precision
   h->prec = DMRG_FP64;
   st = heff_apply_eager(h, psi, y64);
-  h->prec = DMRG_SPLIT_BF16X3;
-  if (st == DMRG_OK) st = heff_apply_eager(h, psi, ys);
   h->prec = keep;
+  if (st == DMRG_OK) st = heff_apply_eager(h, psi, ys);
   double host[2] = {0.0, 0.0};
   if (st == DMRG_OK) {
     diff_kernel<<<grid_for(n), 256, 0, s>>>(y64, n, ys);
@@ -750,7 +749,7 @@ dmrg_status split_floor(dmrg_heff_t h, const double* psi, double* delta) {
 extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts* opts,
                           dmrg_dav_result* res) {
   if (!h || !psi_inout || !opts || !res) return fail(DMRG_EINVAL, "davidson: bad arguments");
-  if (h->prec != DMRG_SPLIT_BF16X3 || opts->fp64_tail <= 0)
+  if (h->prec == DMRG_FP64 || opts->fp64_tail <= 0)
     return solve(h, psi_inout, opts, res, [](const dmrg_dav_result&) { return false; });
   // Split-precision phase until the residual reaches a few times the split
   // matvec's own error (or the tolerance, or stops falling near that level),
@@ -777,10 +776,11 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmr
   dmrg_dav_opts o2 = *opts;
   o2.max_iter = opts->fp64_tail;
   o2.start = 0;  // from the split phase's Ritz vector
+  const int reduced = h->prec;
   h->prec = DMRG_FP64;
   dmrg_dav_result r2{};
   st = solve(h, psi_inout, &o2, &r2, [](const dmrg_dav_result&) { return false; });
-  h->prec = DMRG_SPLIT_BF16X3;
+  h->prec = reduced;
   *res = r2;
   res->iters = r1.iters + r2.iters;
   res->matvecs = r1.matvecs + r2.matvecs + 2;

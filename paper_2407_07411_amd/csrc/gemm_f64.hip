@@ -24,6 +24,7 @@
 namespace dmrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // blockIdx -> logical tile.  Workgroups are dealt round-robin to the 8 XCDs;
 // this remap hands each XCD a contiguous range of the tile table so that
@@ -101,13 +102,15 @@ struct Stage {
 
   __device__ __forceinline__ void advance() { base += kstep; }
 
-  __device__ __forceinline__ void store(double* S, double alpha) const {
+  // Store alpha * value into the LDS tile (double, or rounded to float).
+  template <typename T>
+  __device__ __forceinline__ void store(T* S, double alpha) const {
     if (kc) {
 #pragma unroll
-      for (int r = 0; r < N; ++r) S[lds + r * (NT / BK)] = alpha * v[r];
+      for (int r = 0; r < N; ++r) S[lds + r * (NT / BK)] = (T)(alpha * v[r]);
     } else {
 #pragma unroll
-      for (int r = 0; r < N; ++r) S[lds + r * (NT / ROWS) * (ROWS + 1)] = alpha * v[r];
+      for (int r = 0; r < N; ++r) S[lds + r * (NT / ROWS) * (ROWS + 1)] = (T)(alpha * v[r]);
     }
   }
 };
@@ -236,6 +239,180 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
       }
 }
 
+// FP32-operand form of the same grouped GEMM: operand values are rounded to
+// FP32 while they are staged into LDS and multiplied on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32: twice the FP64 rate); the FP32 partial, times the
+// segment's alpha, is added into an FP64 accumulator at every segment end and
+// every F32_FLUSH_K values of K, which bounds FP32 rounding to that many terms.
+// Lanes as for the FP64 MFMA on the operand side; the four result floats of
+// lane l are D[4(l/16) + v][l%16] (measured).  Tables, tile order, edge-wave
+// skip and load placement are those of the FP64 kernel.
+constexpr int F32_FLUSH_K = 128;
+
+template <int BM, int BN, int BK, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f32_kernel(
+    Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
+    const Tile* __restrict__ tiles, int64_t ntiles) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int FLUSH = F32_FLUSH_K / BK > 0 ? F32_FLUSH_K / BK : 1;
+  static_assert(FM >= 1 && FN >= 1 && BK % 4 == 0, "tile shape");
+  __shared__ float Xs[2][BK][BM + 1];
+  __shared__ float Zs[2][BK][BN + 1];
+
+  const int64_t lt = xcd_remap(blockIdx.x, ntiles);
+  const Tile t = tiles[lt];
+  const Prob p = probs[t.prob];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int NW = WGM * WGN;
+  int wm, wn;
+  if (WGM == 2 && WGN == 4) {
+    const int simd = (wave + (int)(blockIdx.x & 3)) & 3, slot = wave >> 2;
+    wm = slot;
+    wn = slot == 0 ? simd : (simd + 2) & 3;
+  } else {
+    const int role = (wave + 2 * (int)(blockIdx.x & 3)) % NW;
+    wm = role / WGN;
+    wn = role % WGN;
+  }
+  const int m0 = t.tm * BM, n0 = t.tn * BN;
+  const int fr = lane & 15, fk = lane >> 4;
+  const bool active = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
+
+  f4 acc[FM][FN];
+  double acc64[FM][FN][4];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[i][j][v] = 0.f;
+        acc64[i][j][v] = 0.0;
+      }
+
+  const int s_end = p.seg0 + p.nseg;
+  if (p.nseg > 0) {
+    Stage<BM, BK, NT> xs;
+    Stage<BN, BK, NT> zs;
+    int s = p.seg0, k0 = 0, since_flush = 0;
+    Seg g = segs[s];
+    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
+    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+    xs.load(g.K);
+    zs.load(g.K);
+    xs.store(&Xs[0][0][0], 1.0);
+    zs.store(&Zs[0][0][0], 1.0);
+    __syncthreads();
+    int buf = 0;
+    while (true) {
+      int s2 = s, k2 = k0 + BK;
+      Seg g2 = g;
+      if (k2 >= g.K) {
+        ++s2;
+        k2 = 0;
+        if (s2 < s_end) g2 = segs[s2];
+      }
+      const bool more = s2 < s_end;
+      const bool seg_end = s2 != s;
+      if (seg_end) {  // past the last segment g2 == g: harmless, nothing is loaded
+        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
+        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
+      } else {
+        xs.advance();
+        zs.advance();
+      }
+      if (active) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          float a[FM], b[FN];
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kk + fk][wm * WM + i * 16 + fr];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) b[j] = Zs[buf][kk + fk][wn * WN + j * 16 + fr];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      if (more) {
+        xs.load(g2.K - k2);
+        zs.load(g2.K - k2);
+        xs.store(&Xs[buf ^ 1][0][0], 1.0);
+        zs.store(&Zs[buf ^ 1][0][0], 1.0);
+      }
+      if (++since_flush == FLUSH || seg_end) {
+        since_flush = 0;
+        const double al = g.alpha;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              acc64[i][j][v] += al * (double)acc[i][j][v];
+              acc[i][j][v] = 0.f;
+            }
+      }
+      if (!more) break;
+      __syncthreads();
+      buf ^= 1;
+      s = s2;
+      k0 = k2;
+      g = g2;
+    }
+  }
+
+  double* __restrict__ C = bases.p[p.cbuf] + p.coff;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * WM + i * 16 + 4 * fk + v;
+        const int n = n0 + wn * WN + j * 16 + fr;
+        if (m < p.M && n < p.N) {
+          double* c = C + (int64_t)m * p.ldc + n;
+          *c = p.beta ? *c + acc64[i][j][v] : acc64[i][j][v];
+        }
+      }
+}
+
+dmrg_status launch_gemm_f32(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
+                            const Tile* tiles, hipStream_t s) {
+  const Tile* t = tiles + l.tile0;
+  dim3 grid((unsigned)l.ntiles);
+  switch (l.cfg) {
+    case CFG_F64_32:
+      gemm_f32_kernel<32, 32, 32, 1, 1><<<grid, 64, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_F64_64:
+      gemm_f32_kernel<64, 64, 32, 2, 2><<<grid, 256, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_F64_128:
+      gemm_f32_kernel<128, 128, 16, 2, 2><<<grid, 256, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_F64_128W8:
+      gemm_f32_kernel<128, 128, 32, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_F64_256x128:
+      gemm_f32_kernel<256, 128, 16, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_F64_64x128:
+      gemm_f32_kernel<64, 128, 32, 2, 4><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    default:
+      return fail(DMRG_EINVAL, "unknown tile configuration");
+  }
+  DMRG_HIP(hipGetLastError());
+  return DMRG_OK;
+}
+
 int cfg_bm(int cfg) {
   return cfg == CFG_F64_32                                ? 32
          : cfg == CFG_F64_64 || cfg == CFG_F64_64x128     ? 64
@@ -247,7 +424,8 @@ int cfg_bn(int cfg) { return cfg == CFG_F64_32 ? 32 : cfg == CFG_F64_64 ? 64 : 1
 dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                         const Tile* tiles, hipStream_t s) {
   if (l.ntiles <= 0) return DMRG_OK;
-  if (l.split) return launch_gemm_split(l, b, probs, segs, tiles, s);
+  if (l.split == DMRG_SPLIT_BF16X3) return launch_gemm_split(l, b, probs, segs, tiles, s);
+  if (l.split == DMRG_FP32) return launch_gemm_f32(l, b, probs, segs, tiles, s);
   const Tile* t = tiles + l.tile0;
   dim3 grid((unsigned)l.ntiles);
   switch (l.cfg) {

@@ -77,7 +77,7 @@ struct dmrg_heff_s {
   int64_t llen = 0, rlen = 0;
   double flops = 0.0, bytes = 0.0;
   int prec = DMRG_FP64;
-  dmrg::TuneTable tune[2];  // tile shape per (phase, size bucket), per precision
+  dmrg::TuneTable tune[3];  // tile shape per (phase, size bucket), per precision
   int64_t work_budget = 0;  // doubles
   double* work = nullptr;
   int64_t work_elems = 0;
@@ -86,8 +86,9 @@ struct dmrg_heff_s {
   double* adj_part = nullptr;  // the same for the adjoint
   // forward programs, one per precision (tile shapes differ); same waves,
   // workspace offsets and summation order
-  dmrg::Program fwdp[2];
-  dmrg::Program& fwd() { return fwdp[prec == DMRG_SPLIT_BF16X3 ? 1 : 0]; }
+  dmrg::Program fwdp[3];
+  static int prog_index(int p) { return p == DMRG_SPLIT_BF16X3 ? 1 : p == DMRG_FP32 ? 2 : 0; }
+  dmrg::Program& fwd() { return fwdp[prog_index(prec)]; }
   dmrg::Program adj;
   bool adj_built = false;
   int adj_mask = 0;

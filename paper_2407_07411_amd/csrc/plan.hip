@@ -535,7 +535,7 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   if (left_pool_len < 0 || right_pool_len < 0 || (left_pool_len > 0 && !left_pool) ||
       (right_pool_len > 0 && !right_pool))
     return fail(DMRG_EINVAL, "heff_create: bad pool");
-  if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3)
+  if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3 && prec != DMRG_FP32)
     return fail(DMRG_EINVAL, "heff_create: unknown precision");
   std::unique_ptr<dmrg_heff_s> h(new (std::nothrow) dmrg_heff_s);
   if (!h) return fail(DMRG_ENOMEM, "heff_create: out of host memory");
@@ -571,15 +571,15 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   count_work(h.get());
   h->work_budget = workspace_budget_doubles();
   int64_t part_elems = 0;
-  for (int which = 0; which < 2; ++which) {
+  for (int which = 0; which < 3; ++which) {
     if ((st = build_forward(h.get(), cfg_from_env(), which)) != DMRG_OK) return st;
     part_elems = std::max(part_elems, h->fwdp[which].part_elems);
   }
-  for (int which = 0; which < 2; ++which) {
+  for (int which = 0; which < 3; ++which) {
     int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0, part_elems};
     if ((st = h->fwdp[which].validate(len)) != DMRG_OK) return st;
   }
-  for (int which = 0; which < 2 && st == DMRG_OK; ++which) {
+  for (int which = 0; which < 3 && st == DMRG_OK; ++which) {
     st = h->fwdp[which].upload();
     if (st == DMRG_OK && !serial_from_env()) st = h->fwdp[which].prepare_concurrent();
   }
@@ -625,7 +625,7 @@ void dmrg_heff_destroy(dmrg_heff_t h) {
 
 dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec) {
   if (!h) return fail(DMRG_EINVAL, "set_precision: h is NULL");
-  if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3)
+  if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3 && prec != DMRG_FP32)
     return fail(DMRG_EINVAL, "set_precision: unknown precision");
   h->prec = prec;
   return DMRG_OK;
@@ -684,7 +684,9 @@ dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kern
   *n_launches = (int64_t)P.launches.size();
   for (size_t i = 0; i < P.launches.size(); ++i) {
     const Launch& l = P.launches[i];
-    if (kernel) kernel[i] = l.cfg == CFG_REDUCE ? 32 : l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : 0);
+    if (kernel)
+      kernel[i] = l.cfg == CFG_REDUCE ? 32
+                                      : l.cfg + (h->prec == DMRG_SPLIT_BF16X3 ? 16 : h->prec == DMRG_FP32 ? 48 : 0);
     if (flops && l.cfg == CFG_REDUCE) {
       flops[i] = 0.0;
     } else if (flops) {
@@ -796,7 +798,7 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
 extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps) {
   if (!h || !psi || !y || reps < 1 || psi == y) return fail(DMRG_EINVAL, "heff_autotune: bad arguments");
   hipStream_t s = h->ctx->stream;
-  const int which = h->prec == DMRG_SPLIT_BF16X3 ? 1 : 0;
+  const int which = dmrg_heff_s::prog_index(h->prec);
   const Program& P = h->fwdp[which];
   // problems of the current plan grouped by (phase, M bucket, N bucket)
   std::map<int, std::vector<int32_t>> groups;

@@ -13,9 +13,9 @@ from ctypes import byref, c_double, c_int32, c_int64, c_void_p
 import numpy as np
 import torch
 
-from ._lib import (FP64, SPLIT_BF16X3, DavOpts, DavResult, DmrgError, Term, check, lib)
+from ._lib import (FP32, FP64, SPLIT_BF16X3, DavOpts, DavResult, DmrgError, Term, check, lib)
 
-__all__ = ["Context", "Heff", "HeffApply", "davidson", "svd_truncate", "FP64", "SPLIT_BF16X3",
+__all__ = ["Context", "Heff", "HeffApply", "davidson", "svd_truncate", "FP64", "SPLIT_BF16X3", "FP32",
            "DmrgError"]
 
 

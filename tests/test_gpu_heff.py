@@ -190,7 +190,7 @@ def test_split_k_sums(ctx, l24, kchunk, monkeypatch):
     assert rel(gp.cpu().numpy(), pb) <= TOL
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 3])
 def test_two_stream_phases_match_serial(l24, prec, monkeypatch):
     """On a caller stream, each phase runs its smaller tile shapes on a side
     stream next to the largest one, and K-split reductions run next to the

@@ -1,5 +1,7 @@
-"""Split-precision (BF16x3 slices, FP32 accumulation per K tile, FP64
-combine) matvec and Davidson against the FP64 oracle.
+"""Reduced-precision matvecs and Davidson against the FP64 oracle: split
+precision (BF16x3 slices, FP32 accumulation per K chunk, FP64 combine) and
+FP32 operands on the FP32 matrix cores (same accumulation; operands rounded
+to FP32, 2^-24 relative, like the slices), under the same bound.
 
 Stated bound for the matvec: ||y_split - y||_2 <= 1e-5 ||y||_2.  Derivation:
 the slices represent each operand to ~2^-24 relative (FP32 rounding of the
@@ -29,15 +31,16 @@ def ctx():
     return Context(0)
 
 
+@pytest.mark.parametrize("prec", ["split", "fp32"])
 @pytest.mark.parametrize("kind", ["tiny", "l24"])
 @pytest.mark.parametrize("tile", [None, "32", "64", "1288", "256", "64128"])
-def test_split_matvec_bound(ctx, kind, tile, monkeypatch):
-    from paper_2407_07411_amd.heff import SPLIT_BF16X3
-    print("case", kind, tile, flush=True)
+def test_split_matvec_bound(ctx, kind, tile, prec, monkeypatch):
+    from paper_2407_07411_amd.heff import FP32, SPLIT_BF16X3
+    print("case", kind, tile, prec, flush=True)
     if tile:
         monkeypatch.setenv("DMRG_HEFF_TILE", tile)
     prob = tiny_problem(seed=4, L=10, n_elec=9, two_sz=1, D=24, pairs=3) if kind == "tiny" else _l24(2)
-    h = gpu_heff(ctx, prob, prec=SPLIT_BF16X3)
+    h = gpu_heff(ctx, prob, prec=SPLIT_BF16X3 if prec == "split" else FP32)
     y = h.apply(prob.psi.to("cuda")).cpu().numpy()
     ref = heff_apply(prob)
     err = rel(y, ref)
@@ -46,11 +49,12 @@ def test_split_matvec_bound(ctx, kind, tile, monkeypatch):
     assert err > 0.0  # the split kernels ran, not the FP64 ones
 
 
-def test_split_davidson_fp64_tail(ctx):
-    from paper_2407_07411_amd.heff import SPLIT_BF16X3, davidson
+@pytest.mark.parametrize("prec", ["split", "fp32"])
+def test_split_davidson_fp64_tail(ctx, prec):
+    from paper_2407_07411_amd.heff import FP32, SPLIT_BF16X3, davidson
     prob = tiny_problem(seed=6, L=10, n_elec=10, D=24, pairs=3)
     e0 = np.linalg.eigvalsh(heff_dense(prob))[0]
-    h = gpu_heff(ctx, prob, prec=SPLIT_BF16X3)
+    h = gpu_heff(ctx, prob, prec=SPLIT_BF16X3 if prec == "split" else FP32)
     psi = prob.psi.to("cuda").clone()
     res = davidson(h, psi, tol=1e-9, fp64_tail=60)
     print(res, e0, flush=True)

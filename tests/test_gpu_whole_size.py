@@ -9,8 +9,8 @@ few rows and columns of the largest, a middle and the smallest wavefunction
 block (first, last and interior indices, so edge tiles are covered).  Each
 entry must agree to 1e-12 times the sum of the absolute values of the
 products that enter it (the scale of its FP64 rounding error).  The split
-matvec is checked against the FP64 one norm-wise (its stated 1e-5 bound) and
-on the same sampled entries."""
+and FP32-operand matvecs are checked against the FP64 one norm-wise (their
+stated 1e-5 bound) and on the same sampled entries."""
 import gc
 
 import numpy as np
@@ -51,13 +51,18 @@ def test_whole_size_sampled_entries(name):
             ys = torch.empty_like(prob.psi)
             h.set_precision(H.SPLIT_BF16X3)
             h.apply(prob.psi, ys)
+            yf = torch.empty_like(prob.psi)
+            h.set_precision(H.FP32)
+            h.apply(prob.psi, yf)
             h.set_precision(H.FP64)
         torch.cuda.synchronize()
-        split_err = float(torch.linalg.vector_norm(ys - y) / torch.linalg.vector_norm(y))
-        print(name, "split rel err", split_err, flush=True)
-        assert 0.0 < split_err <= SPLIT_TOL
+        for lab, yr in (("split", ys), ("fp32", yf)):
+            err = float(torch.linalg.vector_norm(yr - y) / torch.linalg.vector_norm(y))
+            print(name, lab, "rel err", err, flush=True)
+            assert 0.0 < err <= SPLIT_TOL
         y64 = y.cpu().numpy()
         y16 = ys.cpu().numpy()
+        y32 = yf.cpu().numpy()
         del h, ctx
         lay = layout_of(prob)
         order = sorted(lay.partner, key=lambda a: int(lay.Ld[a]) * int(lay.Rd[lay.partner[a]]))
@@ -69,8 +74,9 @@ def test_whole_size_sampled_entries(name):
             err = np.abs(got - val)
             print(name, "block", b, (nr, nc), "max err", err.max(), "max scale", mag.max(), flush=True)
             assert np.all(err <= 1e-12 * mag + 1e-300)
-            got16 = lay.block(y16, b)[np.ix_(rows, cols)]
-            assert np.all(np.abs(got16 - val) <= SPLIT_TOL * mag + 1e-300)
+            for yr in (y16, y32):
+                got16 = lay.block(yr, b)[np.ix_(rows, cols)]
+                assert np.all(np.abs(got16 - val) <= SPLIT_TOL * mag + 1e-300)
     finally:
         del prob
         gc.collect()
@@ -98,7 +104,8 @@ def test_d8192_graph_davidson_fp64_and_split():
             h = H.Heff(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, prob.terms, prob.left_pool,
                        prob.right_pool)
             out = {}
-            for label, prec, tail in (("fp64", H.FP64, 0), ("split", H.SPLIT_BF16X3, 40)):
+            for label, prec, tail in (("fp64", H.FP64, 0), ("split", H.SPLIT_BF16X3, 40),
+                                      ("fp32", H.FP32, 40)):
                 h.set_precision(prec)
                 psi = prob.psi.clone()
                 out[label] = H.davidson(h, psi, tol=1e-6, max_iter=80, use_graph=True, fp64_tail=tail,
@@ -106,9 +113,10 @@ def test_d8192_graph_davidson_fp64_and_split():
                 print(label, out[label], flush=True)
             h.set_precision(H.FP64)
         torch.cuda.synchronize()
-        assert out["fp64"]["converged"] and out["split"]["converged"]
-        assert out["split"]["split_iters"] >= 1
-        assert abs(out["fp64"]["energy"] - out["split"]["energy"]) < 1e-8
+        for lab in ("split", "fp32"):
+            assert out["fp64"]["converged"] and out[lab]["converged"]
+            assert out[lab]["split_iters"] >= 1
+            assert abs(out["fp64"]["energy"] - out[lab]["energy"]) < 1e-8
         del h, ctx
     finally:
         del prob
