@@ -92,7 +92,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the off-path measurements (SVD truncation, adjoint at L=24)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
+                    help="first copy 1 GiB device to device twice, by the runtime's copy and by an "
+                         "elementwise kernel (reference dispatches for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -117,10 +118,11 @@ def main():
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        dst.copy_(src)  # the runtime's device-to-device copy
+        torch.neg(src, out=dst)  # a plain elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
-        log("copied 1 GiB (counter calibration)")
+        log("copied 1 GiB twice (counter calibration)")
     t0 = time.time()
     prob = make_problem(w["L"], w["n_elec"], w["two_sz"], w["D"], w["seed"], device=dev,
                         pool_budget_bytes=int(args.pool_gb * 1e9))

@@ -114,7 +114,8 @@ typedef struct {
 
 /* Builds the plan: wavefunction layout, the (term, block) work list with the
  * cheaper association order per pair, the grouped-GEMM tile lists and the
- * device workspace.  The pools are borrowed (must outlive the plan, contents
+ * device workspace (intermediates, K-split partial sums, and one vector of
+ * size doubles that holds psi pre-split for split precision).  The pools are borrowed (must outlive the plan, contents
  * may change between applies); pool lengths are in doubles and bound-check
  * every block.  Errors: DMRG_EINVAL, DMRG_EQN (block out of its pool, dq that
  * leaves the basis, odd one-sided term), DMRG_ENOMEM, DMRG_EHIP.
@@ -169,8 +170,8 @@ dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int3
  * (host arrays of at least that many entries) they receive each launch's
  * kernel id (FP64 grouped GEMM tiles 0: 32x32, 1: 64x64, 2: 128x128 with 4
  * waves, 3: 128x128 with 8 waves, 4: 256x128 with 8 waves, 5: 64x128 with 8
- * waves; +16 for the split
- * precision kernels; 32: the ordered reduction of cut K sums) and its
+ * waves; the same shapes +16 for the split precision kernels and +48 for the
+ * FP32-operand kernels; 32: the ordered reduction of cut K sums) and its
  * algorithmic FLOPs (2 M N K summed over its problems, 0 for reductions). */
 dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops);
 /* y = H_eff psi as dmrg_heff_apply (eager), bracketing every launch with HIP

@@ -25,6 +25,13 @@
 // cores work on the current one and one barrier separates K tiles; with one
 // buffer (deeper K tiles) two barriers do.
 //
+// Pre-split operands: the vector and the intermediates of the two-GEMM chains
+// can be held as packed words (three BF16 slices of one value per 64-bit
+// word, made by the same split), written once by the kernel that produces
+// them; staging such an operand only moves the slices into place.  Operator
+// blocks stay FP64 and are split while staged.  Both forms give the same
+// slices, so the results are bit-identical.
+//
 // Matrix core: v_mfma_f32_32x32x16_bf16.  Lanes: A[i][k] holds i = l%32,
 // k = 8(l/32) + e; B[k][j] holds j = l%32, k = 8(l/32) + e (e = 0..7); the 16
 // result floats of lane l are D[8(v/4) + 4(l/32) + v%4][l%32] (measured).
@@ -63,6 +70,38 @@ __device__ __forceinline__ void split_pair(double a, double b, uint32_t& s0, uin
   s2 = pk_bits(h2);
 }
 
+// Packed word of one value from its slices (low, high halves of the pairs
+// made by split_pair: half 0 is the pair's first value).
+__device__ __forceinline__ uint64_t pack_word(uint32_t s0, uint32_t s1, uint32_t s2, int half) {
+  const uint32_t a0 = half ? s0 >> 16 : s0 & 0xffffu;
+  const uint32_t a1 = half ? s1 >> 16 : s1 & 0xffffu;
+  const uint32_t a2 = half ? s2 >> 16 : s2 & 0xffffu;
+  return (uint64_t)(a0 | (a1 << 16)) | ((uint64_t)a2 << 32);
+}
+
+__global__ __launch_bounds__(256) void pack_split_kernel(const double* __restrict__ x,
+                                                          uint64_t* __restrict__ out, int64_t n) {
+  const int64_t np = (n + 1) / 2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = 2 * i;
+    const bool two = j + 1 < n;
+    uint32_t s0, s1, s2;
+    split_pair(x[j], two ? x[j + 1] : 0.0, s0, s1, s2);
+    out[j] = pack_word(s0, s1, s2, 0);
+    if (two) out[j + 1] = pack_word(s0, s1, s2, 1);
+  }
+}
+
+dmrg_status launch_pack_split(const double* x, double* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return DMRG_OK;
+  const int64_t np = (n + 1) / 2;
+  const int64_t blocks = std::min<int64_t>((np + 255) / 256, 2048);
+  pack_split_kernel<<<(unsigned)blocks, 256, 0, s>>>(x, reinterpret_cast<uint64_t*>(out), n);
+  DMRG_HIP(hipGetLastError());
+  return DMRG_OK;
+}
+
 constexpr uint32_t OOB_S = 0xffffffffu;
 
 // The 8-value groups of one operand (ROWS x BK per K tile) that a thread
@@ -82,6 +121,7 @@ struct Stager {
   static constexpr bool EXACT = NG % NT == 0;
   static_assert(EXACT || G == 1, "staging shape");
   const double* base;  // uniform: the block's first row at the current k0
+  bool pk;             // uniform: the operand holds packed words
   int64_t tstep;       // uniform: elements between K tiles
   uint32_t estep;      // uniform: bytes between value e and e + 1 of a group
   uint32_t off[G];     // byte offset of value 0 of each group (OOB outside the problem)
@@ -91,7 +131,8 @@ struct Stager {
   // kc: the operand is contiguous in K (element (row, k) at base + row*ld + k);
   // otherwise it is contiguous in the row index (base + k*ld + row).
   __device__ __forceinline__ void setup(const double* seg, int ld, bool kc, int r0, int nrows,
-                                        int tid) {
+                                        int tid, bool packed) {
+    pk = packed;
     base = kc ? seg + (int64_t)r0 * ld : seg + r0;
     tstep = kc ? (int64_t)BK : (int64_t)BK * ld;
     estep = kc ? 8u * KG : 8u * KG * (uint32_t)ld;
@@ -128,14 +169,26 @@ struct Stager {
 
   __device__ __forceinline__ void advance() { base += tstep; }
 
-  // Split and store into the three slice planes sh[sl][ROWS][LDK].
+  // Split (or unpack) and store into the three slice planes sh[sl][ROWS][LDK].
   __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][LDK], int tid) {
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       if (!EXACT && tid >= NG) continue;
       uint32_t w0[4], w1[4], w2[4];
+      if (pk) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) split_pair(v[r][2 * q], v[r][2 * q + 1], w0[q], w1[q], w2[q]);
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t u = __builtin_bit_cast(uint64_t, v[r][2 * q]);
+          const uint64_t w = __builtin_bit_cast(uint64_t, v[r][2 * q + 1]);
+          const uint32_t ulo = (uint32_t)u, wlo = (uint32_t)w;
+          w0[q] = (ulo & 0xffffu) | (wlo << 16);
+          w1[q] = (ulo >> 16) | (wlo & 0xffff0000u);
+          w2[q] = (uint32_t)(u >> 32) | ((uint32_t)(w >> 32) << 16);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) split_pair(v[r][2 * q], v[r][2 * q + 1], w0[q], w1[q], w2[q]);
+      }
       const u4v s0 = {w0[0], w0[1], w0[2], w0[3]};
       const u4v s1 = {w1[0], w1[1], w1[2], w1[3]};
       const u4v s2 = {w2[0], w2[1], w2[2], w2[3]};
@@ -201,8 +254,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
     Stager<BN, NT, BK> zs;
     int s = p.seg0, k0 = 0, since_flush = 0, buf = 0;
     Seg g = segs[s];
-    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
-    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid, (bases.packed >> g.xbuf) & 1u);
+    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid, (bases.packed >> g.zbuf) & 1u);
     xs.load(g.K);
     zs.load(g.K);
     xs.store(Xh[0], tid);
@@ -220,8 +273,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
       const bool more = s2 < s_end;
       const bool seg_end = s2 != s;
       if (seg_end) {  // past the last segment g2 == g: harmless, nothing is loaded
-        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
-        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
+        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid, (bases.packed >> g2.xbuf) & 1u);
+        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid, (bases.packed >> g2.zbuf) & 1u);
       } else {
         xs.advance();
         zs.advance();
@@ -284,6 +337,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
   }
 
   double* __restrict__ C = bases.p[p.cbuf] + p.coff;
+  if ((bases.packed >> p.cbuf) & 1u) {
+    // a packed output (an intermediate; never accumulated): its split words
+    uint64_t* __restrict__ Cw = reinterpret_cast<uint64_t*>(C);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          uint32_t s0, s1, s2;
+          split_pair(acc64[i][j][v], acc64[i][j][v + 1], s0, s1, s2);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int m = m0 + wm * WM + i * 32 + 8 * ((v + h) / 4) + 4 * (lane >> 5) + ((v + h) % 4);
+            const int n = n0 + wn * WN + j * 32 + fr;
+            if (m < p.M && n < p.N) Cw[(int64_t)m * p.ldc + n] = pack_word(s0, s1, s2, h);
+          }
+        }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll

@@ -40,6 +40,10 @@ enum BufId : uint8_t {
 };
 struct Bases {
   double* p[BUF_COUNT];
+  // Bit b set: buffer b holds pre-split operands, one 64-bit word per value
+  // with its three BF16 slices in bits 0-15, 16-31 and 32-47 (bits 48-63
+  // zero).  Only the split-precision kernel reads or writes such buffers.
+  uint32_t packed = 0;
 };
 
 // One K segment of an output tile:  C += alpha * X (M x K) * Z (K x N).
@@ -142,6 +146,8 @@ struct Program {
 
 dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                         const Tile* tiles, hipStream_t s);
+// Pack n FP64 values into pre-split words (the layout of Bases::packed).
+dmrg_status launch_pack_split(const double* x, double* out, int64_t n, hipStream_t s);
 dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                               const Tile* tiles, hipStream_t s);
 dmrg_status launch_reduce(const Launch& l, const Bases& b, const RedBlock* reds,

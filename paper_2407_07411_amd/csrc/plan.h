@@ -81,6 +81,8 @@ struct dmrg_heff_s {
   int64_t work_budget = 0;  // doubles
   double* work = nullptr;
   int64_t work_elems = 0;
+  double* psi_pk = nullptr;    // pre-split copy of the input vector (split precision)
+  bool split_pack = true;      // split precision stages psi and intermediates pre-split
   double* part = nullptr;      // partials of cut long-K sums (forward)
   int64_t part_elems = 0;      // its length (doubles), the larger of the two programs
   double* adj_part = nullptr;  // the same for the adjoint

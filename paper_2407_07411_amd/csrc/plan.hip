@@ -34,6 +34,13 @@ int64_t workspace_budget_doubles() {
 }
 
 // DMRG_HEFF_SERIAL=1 runs every launch of a matvec in order on one stream.
+// DMRG_HEFF_SPLIT_UNPACKED=1: the split kernels split every operand while
+// staging it (no pre-split vector or intermediates; the same results).
+bool unpacked_from_env() {
+  const char* s = std::getenv("DMRG_HEFF_SPLIT_UNPACKED");
+  return s && std::atoi(s) != 0;
+}
+
 bool serial_from_env() {
   const char* s = std::getenv("DMRG_HEFF_SERIAL");
   return s && std::atoi(s) != 0;
@@ -511,14 +518,37 @@ Bases fwd_bases(dmrg_heff_s* h, const double* psi, double* y) {
   b.p[BUF_RPOOL] = const_cast<double*>(h->rpool);
   b.p[BUF_WORK] = h->work;
   b.p[BUF_PART] = h->part;
+  if (h->prec == DMRG_SPLIT_BF16X3 && h->split_pack) {
+    b.p[BUF_PSI] = h->psi_pk;
+    b.packed = (1u << BUF_PSI) | (1u << BUF_WORK);
+  }
   return b;
+}
+
+// The split program writes its intermediates pre-split: each must be written
+// once, whole (no accumulation, no cut K sum).
+dmrg_status check_packed_outputs(const Program& P) {
+  for (const Prob& p : P.probs)
+    if (p.cbuf == BUF_WORK && p.beta) return fail(DMRG_EQN, "split program: accumulated intermediate");
+  for (const RedBlock& r : P.reds)
+    if (r.cbuf == BUF_WORK) return fail(DMRG_EQN, "split program: cut intermediate");
+  return DMRG_OK;
+}
+
+// Launches the forward program of the current precision needs before its
+// GEMMs: the pre-split copy of psi.
+dmrg_status fwd_prologue(dmrg_heff_s* h, const double* psi, const Bases& b) {
+  if (!((b.packed >> BUF_PSI) & 1u)) return DMRG_OK;
+  return launch_pack_split(psi, h->psi_pk, h->size, h->ctx->stream);
 }
 
 }  // namespace
 
 namespace dmrg {
 dmrg_status heff_apply_eager(dmrg_heff_s* h, const double* psi, double* y) {
-  return h->fwd().run(fwd_bases(h, psi, y), h->ctx->stream, h->prec);
+  const Bases b = fwd_bases(h, psi, y);
+  dmrg_status st = fwd_prologue(h, psi, b);
+  return st != DMRG_OK ? st : h->fwd().run(b, h->ctx->stream, h->prec);
 }
 }  // namespace dmrg
 
@@ -579,6 +609,8 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
     int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0, part_elems};
     if ((st = h->fwdp[which].validate(len)) != DMRG_OK) return st;
   }
+  h->split_pack = !unpacked_from_env();
+  if ((st = check_packed_outputs(h->fwdp[1])) != DMRG_OK) return st;
   for (int which = 0; which < 3 && st == DMRG_OK; ++which) {
     st = h->fwdp[which].upload();
     if (st == DMRG_OK && !serial_from_env()) st = h->fwdp[which].prepare_concurrent();
@@ -599,8 +631,16 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
     (void)hipFree(h->part);
     return fail(DMRG_ENOMEM, "heff_create: workspace allocation failed");
   }
+  if (hipMalloc(&h->psi_pk, h->size * sizeof(double)) != hipSuccess) {
+    h->psi_pk = nullptr;
+    for (auto& p : h->fwdp) p.release();
+    (void)hipFree(h->work);
+    (void)hipFree(h->part);
+    return fail(DMRG_ENOMEM, "heff_create: pre-split vector allocation failed");
+  }
   if ((st = build_diag(h.get())) != DMRG_OK) {
     for (auto& p : h->fwdp) p.release();
+    (void)hipFree(h->psi_pk);
     (void)hipFree(h->work);
     (void)hipFree(h->part);
     return st;
@@ -615,6 +655,7 @@ void dmrg_heff_destroy(dmrg_heff_t h) {
   for (auto& p : h->fwdp) p.release();
   h->adj.release();
   if (h->work) (void)hipFree(h->work);
+  if (h->psi_pk) (void)hipFree(h->psi_pk);
   if (h->adj_work) (void)hipFree(h->adj_work);
   if (h->part) (void)hipFree(h->part);
   if (h->adj_part) (void)hipFree(h->adj_part);
@@ -715,6 +756,7 @@ dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y
   for (size_t i = 0; i <= n && st == DMRG_OK; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) st = fail(DMRG_EHIP, "hipEventCreate failed");
   const Bases b = fwd_bases(h, psi, y);
+  if (st == DMRG_OK) st = fwd_prologue(h, psi, b);
   if (st == DMRG_OK && hipEventRecord(ev[0], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
   for (size_t i = 0; i < n && st == DMRG_OK; ++i) {
     Launch x = P.launches[i];
@@ -829,6 +871,10 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
     return fail(DMRG_EHIP, "heff_autotune: hipEventCreate failed");
   }
   const Bases b = fwd_bases(h, psi, y);
+  if (dmrg_status st = fwd_prologue(h, psi, b); st != DMRG_OK) {
+    cleanup();
+    return st;
+  }
   TuneTable table;
   for (auto& kv : groups) {
     float best = 0.f;
@@ -878,6 +924,7 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
     int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0, h->part_elems};
     st = h->fwdp[which].validate(len);
   }
+  if (st == DMRG_OK && which == 1) st = check_packed_outputs(h->fwdp[which]);
   if (st == DMRG_OK) st = h->fwdp[which].upload();
   if (st == DMRG_OK && !serial_from_env()) st = h->fwdp[which].prepare_concurrent();
   if (st != DMRG_OK) {

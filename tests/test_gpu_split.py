@@ -60,3 +60,40 @@ def test_split_davidson_fp64_tail(ctx, prec):
     print(res, e0, flush=True)
     assert res["converged"] and res["tail_iters"] >= 1
     assert abs(res["energy"] - e0) < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["tiny", "l24"])
+@pytest.mark.parametrize("tile", [None, "32", "64", "64128"])
+def test_presplit_operands_bit_identical(ctx, kind, tile, monkeypatch):
+    """Split precision with the vector and the intermediates held pre-split
+    (packed once by the kernels that produce them) equals the form that
+    splits every operand while staging it, bit for bit: both make the same
+    slices, so every product and every sum is the same.  Eager and graph
+    replays, the graph twice with other work between."""
+    from paper_2407_07411_amd.heff import SPLIT_BF16X3
+    print("case", kind, tile, flush=True)
+    if tile:
+        monkeypatch.setenv("DMRG_HEFF_TILE", tile)
+    prob = tiny_problem(seed=4, L=10, n_elec=9, two_sz=1, D=24, pairs=3) if kind == "tiny" else _l24(2)
+    psi = prob.psi.to("cuda")
+    monkeypatch.setenv("DMRG_HEFF_SPLIT_UNPACKED", "1")
+    h0 = gpu_heff(ctx, prob, prec=SPLIT_BF16X3)
+    ref = h0.apply(psi)
+    monkeypatch.delenv("DMRG_HEFF_SPLIT_UNPACKED")
+    h1 = gpu_heff(ctx, prob, prec=SPLIT_BF16X3)
+    y = h1.apply(psi)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    side = torch.cuda.Stream()  # graphs are captured on a non-default stream
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        h1.use_graph(True)
+        out = torch.empty_like(psi)
+        for _ in range(2):
+            out.zero_()
+            h1.apply(psi, out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref)
+            h0.apply(psi * 0.5)  # other work between the replays
+            torch.cuda.synchronize()
+        h1.use_graph(False)
