@@ -59,9 +59,12 @@ typedef enum {
   DMRG_SPLIT_BF16X3 = 1,  /* operands split into 3 BF16 slices, products of    */
                           /* slice pairs i+j<=2 on BF16 MFMA with FP32          */
                           /* accumulation per K chunk, FP64 combine             */
+  DMRG_SPLIT_FP16X2 = 2,  /* two FP16 slices: not built (FP16's 5-bit exponent */
+                          /* needs per-block scaling); create and              */
+                          /* set_precision return DMRG_ENOTSUP                 */
   DMRG_FP32 = 3           /* operands rounded to FP32, FP32 MFMA               */
                           /* (v_mfma_f32_16x16x4f32), FP32 accumulation per K   */
-                          /* chunk, FP64 combine.  Value 2 is not used.        */
+                          /* chunk, FP64 combine                                */
 } dmrg_prec;
 
 typedef struct dmrg_ctx_s* dmrg_ctx_t;      /* device + borrowed HIP stream      */

@@ -91,7 +91,7 @@ int cfg_bn(int cfg);
 constexpr int32_t CFG_REDUCE = 100;
 struct Launch {
   int32_t cfg;
-  int32_t split;     // 0 FP64, 1 split BF16x3
+  int32_t split;     // kernel family: a dmrg_prec value (FP64, split BF16x3, FP32)
   int64_t tile0;
   int64_t ntiles;
   int32_t phase = 0; // launches of one phase are independent of each other

@@ -565,6 +565,7 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   if (left_pool_len < 0 || right_pool_len < 0 || (left_pool_len > 0 && !left_pool) ||
       (right_pool_len > 0 && !right_pool))
     return fail(DMRG_EINVAL, "heff_create: bad pool");
+  if (prec == DMRG_SPLIT_FP16X2) return fail(DMRG_ENOTSUP, "heff_create: FP16x2 split precision is not built");
   if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3 && prec != DMRG_FP32)
     return fail(DMRG_EINVAL, "heff_create: unknown precision");
   std::unique_ptr<dmrg_heff_s> h(new (std::nothrow) dmrg_heff_s);
@@ -666,6 +667,7 @@ void dmrg_heff_destroy(dmrg_heff_t h) {
 
 dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec) {
   if (!h) return fail(DMRG_EINVAL, "set_precision: h is NULL");
+  if (prec == DMRG_SPLIT_FP16X2) return fail(DMRG_ENOTSUP, "set_precision: FP16x2 split precision is not built");
   if (prec != DMRG_FP64 && prec != DMRG_SPLIT_BF16X3 && prec != DMRG_FP32)
     return fail(DMRG_EINVAL, "set_precision: unknown precision");
   h->prec = prec;

@@ -98,3 +98,29 @@ def test_invalid_offsets_rejected_on_host(ctx):
     with pytest.raises(DmrgError) as e:
         _heff(ctx, _with_terms(prob, [far]))
     assert e.value.status == DMRG_EQN
+
+
+def test_unbuilt_and_unknown_precisions_rejected(ctx):
+    """The FP16x2 split value of the precision enum is declared but not
+    built: plan creation and set_precision return DMRG_ENOTSUP; values outside
+    the enum are DMRG_EINVAL.  Both are refused before any allocation or
+    launch, and a refused set_precision leaves the plan's precision as it was."""
+    from paper_2407_07411_amd._lib import DmrgError
+    from paper_2407_07411_amd.heff import FP64
+    DMRG_EINVAL, DMRG_ENOTSUP = -1, -6
+    print("case precisions", flush=True)
+    prob = tiny_problem(seed=9)
+    for prec, status in ((2, DMRG_ENOTSUP), (7, DMRG_EINVAL)):
+        with pytest.raises(DmrgError) as e:
+            _heff(ctx, prob, prec=prec)
+        assert e.value.status == status
+    h = _heff(ctx, prob, prec=FP64)
+    psi = prob.psi.to("cuda")
+    y0 = h.apply(psi)
+    for prec, status in ((2, DMRG_ENOTSUP), (7, DMRG_EINVAL)):
+        with pytest.raises(DmrgError) as e:
+            h.set_precision(prec)
+        assert e.value.status == status
+    y1 = h.apply(psi)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
