@@ -153,18 +153,27 @@ def test_physical_centre_matvec(ctx):
     assert rel(y, heff_apply(prob, x)) <= TOL
 
 
-def test_autotune_keeps_results(ctx, l24):
-    """Tile shapes change only the tiling, not any element's summation
-    order (same K sequence, same 4-deep MFMA steps), so the autotuned plan
-    reproduces the default plan bit for bit."""
-    h = gpu_heff(ctx, l24)
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_autotune_keeps_results(ctx, l24, prec):
+    """FP64 and FP32 operands: tile shapes change only the tiling, not any
+    element's summation order (same K sequence, same 4-deep MFMA steps, FP32
+    partials flushed every 128 K values), so the autotuned plan reproduces the
+    default plan bit for bit.  Split precision: the BF16 MFMAs sum 16 K values
+    in an order set by the K tile depth, which differs between shapes, so the
+    tuned plan is held to the split bound instead."""
+    print("case autotune prec", prec, flush=True)
+    h = gpu_heff(ctx, l24, prec=prec)
     x = l24.psi.to("cuda")
     y0 = h.apply(x).clone()
     h.autotune(x, reps=2)
     y1 = h.apply(x)
     torch.cuda.synchronize()
-    assert torch.equal(y0, y1)
-    assert rel(y1.cpu().numpy(), heff_apply(l24)) <= TOL
+    ref = heff_apply(l24)
+    if prec == 1:
+        assert rel(y1.cpu().numpy(), ref) <= 1e-5
+    else:
+        assert torch.equal(y0, y1)
+        assert rel(y1.cpu().numpy(), ref) <= (TOL if prec == 0 else 1e-5)
 
 
 @pytest.mark.parametrize("kchunk", ["64", "700"])
