@@ -165,7 +165,8 @@ dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable);
  * shape per group and rebuilds the plan with it.  The timing runs the
  * current precision's kernels on the context stream with psi and y (device
  * double[size]; y and the workspace are overwritten).  reps >= 1 timed
- * launches per candidate.  Synchronises. */
+ * launches per candidate.  The adjoint keeps the built-in rule.
+ * Synchronises. */
 dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps);
 
 /* Profiling: the matvec is a fixed sequence of grouped-GEMM launches.
@@ -203,8 +204,9 @@ typedef struct {
   int32_t matvecs;
   int32_t converged;
   int32_t tail_iters;    /* iterations spent in the FP64 tail                 */
-  double split_residual; /* residual where the split-precision phase ended   */
-  int32_t split_iters;   /* iterations of the split-precision phase          */
+  double split_residual; /* residual where the reduced-precision phase ended */
+  int32_t split_iters;   /* iterations of the reduced-precision phase (split */
+                         /* or FP32 operands)                                 */
   int32_t reserved;
 } dmrg_dav_result;
 

@@ -331,7 +331,10 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
 dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
-  pb.tune = &h->tune[0];
+  // built-in tile rule: the forward program's tuned table was measured on
+  // other shapes (gradient blocks are operator-shaped with short K) and made
+  // the adjoint slower
+  pb.tune = nullptr;
   const int64_t nitems = (int64_t)h->items.size();
   std::vector<int64_t> woff(nitems, -1);
   int64_t budget = std::max<int64_t>(h->work_budget, 1);
