@@ -115,8 +115,11 @@ struct Stage {
   }
 };
 
+// The 64 x 128 shape is held to 80 VGPRs: six waves per SIMD, which its LDS
+// footprint (three workgroups per CU) allows.
 template <int BM, int BN, int BK, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f64_kernel(
     Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
     const Tile* __restrict__ tiles, int64_t ntiles) {
   constexpr int NT = 64 * WGM * WGN;
@@ -152,11 +155,28 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
   const int fr = lane & 15, fk = lane >> 4;
   const bool active = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
 
+  // An accumulating output starts from its old values, loaded here so that
+  // their latency overlaps the first K tile (loading them in the epilogue
+  // would wait on each one: a store may alias the next load).  Lanes outside
+  // the problem read its last row or column and store nothing.
   d4 acc[FM][FN];
+  double* __restrict__ C = bases.p[p.cbuf] + p.coff;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  if (p.beta) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = min(m0 + wm * WM + i * 16 + fk + 4 * v, p.M - 1);
+          const int n = min(n0 + wn * WN + j * 16 + fr, p.N - 1);
+          acc[i][j][v] = C[(int64_t)m * p.ldc + n];
+        }
+  }
 
   const int s_end = p.seg0 + p.nseg;
   if (p.nseg > 0) {
@@ -223,7 +243,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
     }
   }
 
-  double* __restrict__ C = bases.p[p.cbuf] + p.coff;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -232,10 +251,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_kernel(
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm * WM + i * 16 + fk + 4 * v;
         const int n = n0 + wn * WN + j * 16 + fr;
-        if (m < p.M && n < p.N) {
-          double* c = C + (int64_t)m * p.ldc + n;
-          *c = p.beta ? *c + acc[i][j][v] : acc[i][j][v];
-        }
+        if (m < p.M && n < p.N) C[(int64_t)m * p.ldc + n] = acc[i][j][v];
       }
 }
 
