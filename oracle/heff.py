@@ -93,15 +93,23 @@ def term_items(lay: Layout, t):
         c = lay.partner[a]
         q_n = int(lay.Lq[a][0])
         s = -1.0 if (t.odd and q_n % 2) else 1.0
+        # One-sided terms are particle-number conserving (even), so their
+        # hermitian-conjugate partner is the transposed block with +c.
         if t.one_sided == 1:
             off = int(t.left_off[a])
             if off >= 0:
-                items.append((a, a, ("L", off, int(lay.Ld[a]), int(lay.Ld[a])), False, None, False, t.coeff))
+                A = ("L", off, int(lay.Ld[a]), int(lay.Ld[a]))
+                items.append((a, a, A, False, None, False, t.coeff))
+                if t.hc:
+                    items.append((a, a, A, True, None, False, t.coeff))
             continue
         if t.one_sided == 2:
             off = int(t.right_off[c])
             if off >= 0:
-                items.append((a, a, None, False, ("R", off, int(lay.Rd[c]), int(lay.Rd[c])), False, t.coeff))
+                B = ("R", off, int(lay.Rd[c]), int(lay.Rd[c]))
+                items.append((a, a, None, False, B, False, t.coeff))
+                if t.hc:
+                    items.append((a, a, None, False, B, True, t.coeff))
             continue
         b = lay.shift_left(a, t.dq)
         if b is None or b not in lay.partner:
@@ -199,6 +207,22 @@ def count_flops(prob):
                 total += min(2 * dl2 * dl * dr + 2 * dl2 * dr * dr2,
                              2 * dl * dr * dr2 + 2 * dl2 * dl * dr2)
     return total
+
+
+def count_bytes(prob):
+    """Algorithmic bytes of one matvec: every stored operator block that some
+    (term, block) pair uses, read once (a block shared by several terms or by
+    a term and its hermitian-conjugate partner counts once), plus psi read
+    and y written; 8 bytes per double."""
+    lay = layout_of(prob)
+    used = {}
+    for t in prob.terms:
+        for (a, b, A, tA, B, tB, alpha) in term_items(lay, t):
+            for spec in (A, B):
+                if spec is not None:
+                    kind, off, rows, cols = spec
+                    used[(kind, off)] = rows * cols
+    return 8 * (sum(used.values()) + 2 * lay.total)
 
 
 def _stored_rows(pool, spec, trans, rows):

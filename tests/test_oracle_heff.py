@@ -15,11 +15,11 @@ import torch
 
 from oracle.davidson import davidson
 from oracle.fci import fci_energy, fci_hamiltonian
-from oracle.heff import count_flops, heff_apply, heff_dense, heff_diag, layout_of
+from oracle.heff import count_bytes, count_flops, heff_apply, heff_dense, heff_diag, layout_of
 from oracle.physical import embedding, physical_problem
 from synth.integrals import integrals
 from synth.problem import Problem, Term
-from tests.conftest import tiny_problem
+from tests.conftest import tiny_problem, with_one_sided_hc
 
 
 def kron_dense(prob):
@@ -66,9 +66,12 @@ def kron_dense(prob):
     return H[np.ix_(sel, sel)]
 
 
+@pytest.mark.parametrize("one_sided_hc", [False, True])
 @pytest.mark.parametrize("seed,D,two_sz", [(1, 4, 0), (2, 6, 0), (3, 5, 2)])
-def test_matvec_equals_kron_assembly(seed, D, two_sz):
+def test_matvec_equals_kron_assembly(seed, D, two_sz, one_sided_hc):
     prob = tiny_problem(seed=seed, D=D, two_sz=two_sz, pairs=2)
+    if one_sided_hc:
+        prob = with_one_sided_hc(prob, seed=seed)
     H1 = heff_dense(prob)
     H2 = kron_dense(prob)
     assert np.abs(H1 - H2).max() <= 1e-13 * max(1.0, np.abs(H2).max())
@@ -93,8 +96,11 @@ def test_hermitian_and_linear():
     assert np.allclose(y3 - yr, 3.0 * (y1 - yr), rtol=0, atol=1e-12)
 
 
-def test_diag_matches_dense():
+@pytest.mark.parametrize("one_sided_hc", [False, True])
+def test_diag_matches_dense(one_sided_hc):
     prob = tiny_problem(seed=5, D=8, pairs=3)
+    if one_sided_hc:
+        prob = with_one_sided_hc(prob, seed=5)
     assert np.abs(heff_diag(prob) - np.diag(heff_dense(prob))).max() < 1e-13
 
 
@@ -176,6 +182,63 @@ def test_flop_count_by_hand():
                    torch.from_numpy(rng.standard_normal(9)), torch.from_numpy(rng.standard_normal(16)),
                    torch.zeros(12, dtype=torch.float64))
     assert count_flops(prob) == 2 * 168
+    # bytes: A (9) and B (16) read once (the hc partner reuses them), psi
+    # read and y written (12 each)
+    assert count_bytes(prob) == 8 * (9 + 16 + 2 * 12)
+
+
+def _rect_problem(one_sided=0, hc=0):
+    """Two left sectors (1,1) d=3 and (2,0) d=2, two right sectors (2,0) d=4
+    and (1,1) d=5, total Q = (3,1): psi blocks 3x4 (a0, c0) and 2x5 (a1, c1)."""
+    rng = np.random.default_rng(5)
+    Lq = np.array([[1, 1], [2, 0]], dtype=np.int32)
+    Rq = np.array([[2, 0], [1, 1]], dtype=np.int32)
+    Ld, Rd = np.array([3, 2]), np.array([4, 5])
+    if one_sided == 0:
+        # dq = (1,-1), odd: O^L[a1, a0] is 2x3, O^R[c1, c0] is 5x4
+        t = Term(dq=(1, -1), odd=1, hc=hc, one_sided=0, coeff=0.5,
+                 left_off=np.array([0, -1]), right_off=np.array([0, -1]))
+        lp, rp = rng.standard_normal(6), rng.standard_normal(20)
+    elif one_sided == 1:
+        t = Term(dq=(0, 0), odd=0, hc=hc, one_sided=1, coeff=0.5,
+                 left_off=np.array([0, 9]), right_off=None)
+        lp, rp = rng.standard_normal(13), rng.standard_normal(1)
+    else:
+        t = Term(dq=(0, 0), odd=0, hc=hc, one_sided=2, coeff=0.5,
+                 left_off=None, right_off=np.array([0, 16]))
+        lp, rp = rng.standard_normal(1), rng.standard_normal(41)
+    return Problem(Lq, Ld, Rq, Rd, np.array([3, 1], dtype=np.int32), [t], torch.from_numpy(lp),
+                   torch.from_numpy(rp), torch.from_numpy(rng.standard_normal(22)))
+
+
+@pytest.mark.parametrize("hc", [0, 1])
+def test_flop_count_rectangular_shift_by_hand(hc):
+    # item (a0,c0) 3x4 -> (a1,c1) 2x5 with A 2x3, B 5x4:
+    #   left-first  A Psi: 2*2*3*4 = 48, then (2x4) B^T: 2*2*4*5 = 80 -> 128
+    #   right-first Psi B^T: 2*3*4*5 = 120, then A (3x5): 2*2*3*5 = 60 -> 180
+    # partner (a1,c1) 2x5 -> (a0,c0) 3x4 with A^T 3x2, B^T 4x5:
+    #   left-first  A^T Psi: 2*3*2*5 = 60, then (3x5) B: 2*3*5*4 = 120 -> 180
+    #   right-first Psi B: 2*2*5*4 = 80, then A^T (2x4): 2*3*2*4 = 48 -> 128
+    prob = _rect_problem(0, hc)
+    assert count_flops(prob) == 128 * (1 + hc)
+    # both items read the same two stored blocks: 6 + 20 doubles, psi 22
+    assert count_bytes(prob) == 8 * (6 + 20 + 2 * 22)
+    # the item list behind it: the dense operator has exactly these blocks
+    H = heff_dense(prob)
+    assert np.count_nonzero(H[12:, :12]) == 10 * 12
+    assert np.count_nonzero(H[:12, 12:]) == (12 * 10 if hc else 0)
+
+
+@pytest.mark.parametrize("one_sided", [1, 2])
+@pytest.mark.parametrize("hc", [0, 1])
+def test_flop_count_one_sided_by_hand(one_sided, hc):
+    # left only: A_q Psi_q per block, 2*3*3*4 = 72 and 2*2*2*5 = 40;
+    # right only: Psi_q B_q^T, 2*3*4*4 = 96 and 2*2*5*5 = 100; hc doubles
+    prob = _rect_problem(one_sided, hc)
+    per = 72 + 40 if one_sided == 1 else 96 + 100
+    assert count_flops(prob) == per * (1 + hc)
+    blocks = 9 + 4 if one_sided == 1 else 16 + 25
+    assert count_bytes(prob) == 8 * (blocks + 2 * 22)
 
 
 @pytest.mark.parametrize("seed,D,two_sz", [(4, 6, 0), (5, 5, 2)])

@@ -15,7 +15,7 @@ from oracle.davidson import davidson
 from oracle.grad import heff_adjoint
 from oracle.heff import heff_apply, heff_dense, heff_diag, layout_of
 from oracle.svd import reconstruct, svd_truncate
-from tests.conftest import tiny_problem
+from tests.conftest import tiny_problem, with_one_sided_hc
 
 
 @pytest.mark.parametrize("max_subspace", [24, 5])
@@ -60,8 +60,11 @@ def _dot(a, b):
     return float(np.dot(np.ravel(a), np.ravel(b)))
 
 
-def test_adjoint_euler_identities():
+@pytest.mark.parametrize("one_sided_hc", [False, True])
+def test_adjoint_euler_identities(one_sided_hc):
     prob = tiny_problem(seed=9, D=10, pairs=3)
+    if one_sided_hc:
+        prob = with_one_sided_hc(prob, seed=9)
     lay = layout_of(prob)
     rng = np.random.default_rng(1)
     psi = rng.standard_normal(lay.total)
@@ -80,8 +83,11 @@ def test_adjoint_euler_identities():
     assert np.abs(pb - heff_dense(prob).T @ ybar).max() < 1e-12
 
 
-def test_adjoint_central_differences():
+@pytest.mark.parametrize("one_sided_hc", [False, True])
+def test_adjoint_central_differences(one_sided_hc):
     prob = tiny_problem(seed=10, D=8, pairs=2)
+    if one_sided_hc:
+        prob = with_one_sided_hc(prob, seed=10)
     lay = layout_of(prob)
     rng = np.random.default_rng(2)
     psi = rng.standard_normal(lay.total)
