@@ -183,6 +183,9 @@ def main():
         roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                         frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=traffic,
                         traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                        traffic_source="read from the committed counter summary of this workload while the "
+                                       "kernel, plan and generator sources match its SHA-256 (else null); "
+                                       "not counted in this run",
                         kernel=dname, launches=dn,
                         avg_launch_ms=round(dms / dn, 4), flops_per_launch=dflops / dn,
                         share_of_matvec=round(dms / float(ms.sum()), 3))
@@ -276,7 +279,11 @@ def main():
             for lab in ("split", "fp32"):
                 r = extra[f"davidson_{lab}_fp64_tail"]
                 if extra["davidson_fp64"]["converged"] and r["converged"]:
-                    extra[f"{lab}_energy_error"] = abs(extra["davidson_fp64"]["energy"] - r["energy"])
+                    e64 = extra["davidson_fp64"]["energy"]
+                    extra[f"{lab}_energy_error"] = abs(e64 - r["energy"])
+                    # the reduced-precision phase alone, before the FP64 tail
+                    extra[f"{lab}_only_energy_error"] = abs(e64 - r["split_energy"])
+                    extra[f"{lab}_only_residual"] = r["split_residual"]
                     extra[f"{lab}_solve_speedup"] = round(extra["davidson_fp64"]["seconds"] / r["seconds"], 3)
 
         # ---- off the timed path, measured: SVD truncation of the FP64 ground state
@@ -297,6 +304,8 @@ def main():
             del U, S, Vt
     if not args.no_extra:
         extra["adjoint_l24_d1024"] = adjoint_timing(dev)
+        # the L=24, D=1024 single FP64 matvec with all 1226 terms, on its own
+        extra["matvec_tflops_l24_d1024_all_terms"] = extra["adjoint_l24_d1024"]["forward_tflops"]
         extra["sweeps_l8_d64"] = sweep_timing()
 
     cpu = None
@@ -437,8 +446,34 @@ def _cpu_sample(prob, terms, target_s):
             break
     n_terms = sum(1 + t.hc for t in prob.terms)
     return dict(value=round(flops / secs / 1e12, 5), unit="TFLOPS", cores=int(cores), kind="oracle",
+                cpu_model=_cpu_model(), blas=_blas_vendor(),
                 sample=f"{n} operator pairs (with their hc partners) of {n_terms} terms, full sector shapes, "
                        f"numpy float64 matvec, {secs:.1f} s")
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _blas_vendor():
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if libs:
+            i = libs[0]
+            return f"{i.get('internal_api')} {i.get('version')} ({i.get('threading_layer')}, " \
+                   f"{i.get('num_threads')} threads)"
+    except Exception:  # pragma: no cover
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

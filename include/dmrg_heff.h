@@ -48,7 +48,8 @@ typedef enum {
                       /* block outside its pool, odd parity on a one-sided op) */
   DMRG_ENOMEM = -3,   /* device or host allocation failed                      */
   DMRG_EHIP = -4,     /* a HIP runtime call or kernel launch failed            */
-  DMRG_ENOCONV = -5,  /* Davidson stopped before reaching the tolerance        */
+  DMRG_ENOCONV = -5,  /* an iteration (Davidson, SVD sweeps) stopped before    */
+                      /* reaching its tolerance                                */
   DMRG_ENOTSUP = -6   /* combination not supported by this library             */
 } dmrg_status;
 
@@ -137,13 +138,23 @@ dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec);
 dmrg_status dmrg_heff_flops(dmrg_heff_t h, double* alg_flops, double* alg_bytes);
 /* Length of psi in doubles (== dmrg_wfn_layout total). */
 int64_t dmrg_heff_size(dmrg_heff_t h);
-/* y = H_eff psi.  psi and y: device double[size], must not overlap. */
+/* y = H_eff psi: the operator of the local eigenproblem that each MPS update
+ * solves (Eq. 2; the Lanczos/Davidson step that takes about 80% of the run
+ * time, Numerical procedure section), as the operator-pair sum stated at the
+ * top of this file.  psi and y: device double[size], must not overlap.
+ * Errors: DMRG_EINVAL (null or aliasing pointers; graph mode on the null
+ * stream), DMRG_EHIP.  Data are not validated. */
 dmrg_status dmrg_heff_apply(dmrg_heff_t h, const double* psi, double* y);
-/* diag = diagonal of H_eff (device double[size]): only dq = 0 pairs reach
- * the diagonal, each as c * diag(O^L) (x) diag(O^R). */
+/* diag = diagonal of H_eff (device double[size]), the Davidson
+ * preconditioner of the local eigenproblem (Eq. 2; Numerical procedure
+ * section): only dq = 0 pairs reach the diagonal, each as
+ * c * diag(O^L) (x) diag(O^R) (a transposed hc partner has the same
+ * diagonal).  Errors: DMRG_EINVAL, DMRG_EHIP. */
 dmrg_status dmrg_heff_diag(dmrg_heff_t h, double* diag);
 /* Adjoint of y = H_eff(O) psi for an upstream gradient ybar (device
- * double[size]).  Each non-null output is ACCUMULATED (+=):
+ * double[size]): the gradients with respect to the wavefunction and to the
+ * operator blocks that an orbital gradient needs (DMRG-CASSCF, named in the
+ * P450 section of the paper).  Each non-null output is ACCUMULATED (+=):
  *   psibar         += H_eff^T ybar                      (device double[size])
  *   left_pool_bar  += d<ybar, y>/d left_pool   (device, left_pool layout)
  *   right_pool_bar += d<ybar, y>/d right_pool  (device, right_pool layout)
@@ -208,6 +219,8 @@ typedef struct {
   int32_t split_iters;   /* iterations of the reduced-precision phase (split */
                          /* or FP32 operands)                                 */
   int32_t reserved;
+  double split_energy;   /* Ritz value where the reduced-precision phase     */
+                         /* ended, before the FP64 tail                       */
 } dmrg_dav_result;
 
 /* Davidson (E. R. Davidson 1975) for the lowest eigenpair of H_eff with the
@@ -232,7 +245,10 @@ dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts*
                           dmrg_dav_result* res);
 
 /* ---- SVD truncation --------------------------------------------------------- */
-/* Factorises each block Psi[q, Q-q] = U S V^T (one-sided Jacobi, FP64),
+/* The matrix factorisation that follows each local optimisation
+ * (Introduction) with D states kept, D setting the accuracy (Numerical
+ * procedure section).
+ * Factorises each block Psi[q, Q-q] = U S V^T (one-sided Jacobi, FP64),
  * pools all singular values, sorts them descending (ties: lower left-sector
  * index first, then position) and keeps at most max_keep values > cutoff.
  * psi: device double[size] in the layout of (L, R, Q).
@@ -243,7 +259,10 @@ dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmrg_dav_opts*
  *   block), Vt block k_q x d_R(Q-q) row-major; capacities u_cap, s_cap,
  *   vt_cap in doubles (DMRG_EINVAL if too small; the needed sizes are what
  *   the call would write with max_keep = total rank).
- * trunc_err (host): sum of discarded sigma^2.  Synchronises. */
+ * trunc_err (host): sum of discarded sigma^2.  Synchronises.
+ * Errors: DMRG_EINVAL, DMRG_ENOMEM, DMRG_EHIP; DMRG_ENOCONV when a block
+ * still rotates after 80 Jacobi sweeps (the outputs are written but not
+ * converged). */
 dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
                               const double* psi, int64_t max_keep, double cutoff,
                               int64_t* kept_dim, double* U, int64_t u_cap, double* S,

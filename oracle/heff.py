@@ -269,3 +269,78 @@ def heff_entries(prob, b, rows, cols, psi=None):
             val += alpha * v
             mag += abs(alpha) * m
     return val, mag
+
+
+def _rows_of(pool, spec, trans, rows_per_item):
+    """Rows of op(stored block) for many items of one stored-block shape
+    class: spec[i] = (kind, off, nr, nc) with the same row length, rows
+    `rows_per_item` (a list of row indices, the same for every item).
+    Returns float64 numpy of shape (n_items, len(rows), row_length).  Only
+    the needed entries leave the pool (one gather per call)."""
+    offs = np.array([s[1] for s in spec], dtype=np.int64)
+    nr = np.array([s[2] for s in spec], dtype=np.int64)
+    nc = np.array([s[3] for s in spec], dtype=np.int64)
+    tr = np.array(trans, dtype=bool)
+    r = np.asarray(rows_per_item, dtype=np.int64)
+    length = np.where(tr, nr, nc)
+    assert np.all(length == length[0])
+    k = np.arange(int(length[0]), dtype=np.int64)
+    # not transposed: element (r, k) of the stored block at off + r * nc + k
+    # transposed:     element (k, r) of the stored block at off + k * nc + r
+    start = offs[:, None] + np.where(tr[:, None], r[None, :], r[None, :] * nc[:, None])
+    step = np.where(tr, nc, 1)
+    idx = start[:, :, None] + step[:, None, None] * k[None, None, :]
+    if hasattr(pool, "detach"):  # a (device) tensor: gather there, copy the entries only
+        import torch
+        ti = torch.from_numpy(idx.reshape(-1)).to(pool.device)
+        return pool.detach().index_select(0, ti).cpu().numpy().astype(np.float64).reshape(idx.shape)
+    return np.asarray(pool)[idx].astype(np.float64)
+
+
+def heff_entries_blocks(prob, samples, psi=None):
+    """heff_entries for many output blocks at once: samples maps an output
+    left sector b to (rows, cols); returns {b: (val, mag)}.
+
+    Same definition and the same per-item products as heff_entries,
+    y_b[rows, cols] = sum over items of alpha * op(A)[rows, :] X_a op(B)[cols, :]^T,
+    with the items gathered per (input block, output block, item kind) so
+    that each group is one stacked numpy product (the sum over items is
+    then taken group by group instead of in term order: an FP64 rounding
+    difference only)."""
+    lay = layout_of(prob)
+    pools = {"L": prob.left_pool, "R": prob.right_pool}
+    x = _np(prob.psi if psi is None else psi).astype(np.float64)
+    groups = {}
+    for t in prob.terms:
+        for (a, b, A, tA, B, tB, alpha) in term_items(lay, t):
+            if b not in samples:
+                continue
+            kind = 0 if (A is not None and B is not None) else (1 if B is None else 2)
+            groups.setdefault((a, b, kind), []).append((A, tA, B, tB, alpha))
+    out = {}
+    for b, (rows, cols) in samples.items():
+        out[b] = (np.zeros((len(rows), len(cols))), np.zeros((len(rows), len(cols))))
+    for (a, b, kind), items in groups.items():
+        rows, cols = samples[b]
+        rows, cols = list(rows), list(cols)
+        X = lay.block(x, a)
+        al = np.array([it[4] for it in items])
+        if kind != 2:  # op(A)[rows, :] of every item: (n, |rows|, d_L(a))
+            A_ = _rows_of(pools["L"], [it[0] for it in items], [it[1] for it in items], rows)
+        if kind != 1:  # op(B)[cols, :] of every item: (n, |cols|, d_R(c))
+            B_ = _rows_of(pools["R"], [it[2] for it in items], [it[3] for it in items], cols)
+        if kind == 0:
+            P = (A_.reshape(-1, X.shape[0]) @ X).reshape(len(items), len(rows), -1)
+            Pm = (np.abs(A_).reshape(-1, X.shape[0]) @ np.abs(X)).reshape(len(items), len(rows), -1)
+            v = np.einsum("nrk,nck->nrc", P, B_)
+            m = np.einsum("nrk,nck->nrc", Pm, np.abs(B_))
+        elif kind == 1:
+            v = A_ @ X[:, cols][None, :, :]
+            m = np.abs(A_) @ np.abs(X[:, cols])[None, :, :]
+        else:
+            v = np.einsum("rk,nck->nrc", X[rows, :], B_)
+            m = np.einsum("rk,nck->nrc", np.abs(X[rows, :]), np.abs(B_))
+        val, mag = out[b]
+        val += np.einsum("n,nrc->rc", al, v)
+        mag += np.einsum("n,nrc->rc", np.abs(al), m)
+    return out

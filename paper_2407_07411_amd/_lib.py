@@ -28,7 +28,8 @@ class DavOpts(ctypes.Structure):
 class DavResult(ctypes.Structure):
     _fields_ = [("energy", c_double), ("residual", c_double), ("iters", c_int32),
                 ("matvecs", c_int32), ("converged", c_int32), ("tail_iters", c_int32),
-                ("split_residual", c_double), ("split_iters", c_int32), ("reserved", c_int32)]
+                ("split_residual", c_double), ("split_iters", c_int32), ("reserved", c_int32),
+                ("split_energy", c_double)]
 
 
 class DmrgError(RuntimeError):

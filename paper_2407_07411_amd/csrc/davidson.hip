@@ -787,5 +787,6 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff_t h, double* psi_inout, const dmr
   res->tail_iters = r2.iters;
   res->split_iters = r1.iters;
   res->split_residual = r1.residual;
+  res->split_energy = r1.energy;
   return st;
 }

@@ -20,6 +20,11 @@
 
 namespace dmrg {
 
+// Sweeps after which a block that still rotates is reported as not
+// converged (DMRG_ENOCONV).  Quadratic convergence makes the usual count
+// about ten; decaying spectra spanning the whole FP64 range need more.
+constexpr int SVD_MAX_SWEEPS = 80;
+
 struct SvdBlock {
   int64_t src;    // offset of the block in psi (row-major m x n)
   int64_t boff;   // work: B, column-major r x c (r >= c)
@@ -81,14 +86,16 @@ struct SvdPair {
 // wavefront per column pair; the pairs of a round are disjoint, so the
 // rotations of a launch commute and the result does not depend on how waves
 // are scheduled.  A pair rotates when its columns are not orthogonal to
-// relative tolerance tol; V accumulates the rotations; flags[blk] records
-// that the block rotated in this sweep.  Rotation of the 2x2 Gram matrix
-// [[alpha, gamma], [gamma, beta]] by the standard formulas.
+// relative tolerance eps * sqrt(r) (r the column length: the rounding level
+// of a computed inner product, the usual one-sided Jacobi criterion); V
+// accumulates the rotations; flags[blk] records that the block rotated in
+// this sweep.  Rotation of the 2x2 Gram matrix [[alpha, gamma], [gamma, beta]]
+// by the standard formulas.
 __global__ __launch_bounds__(256) void svd_round_kernel(const SvdBlock* __restrict__ blocks,
                                                         const SvdPair* __restrict__ pairs,
                                                         int64_t npairs, int rd,
                                                         double* __restrict__ work,
-                                                        int32_t* __restrict__ flags, double tol) {
+                                                        int32_t* __restrict__ flags, double eps) {
   const int lane = threadIdx.x & 63;
   const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (wid >= npairs) return;
@@ -114,7 +121,7 @@ __global__ __launch_bounds__(256) void svd_round_kernel(const SvdBlock* __restri
   al = wave_sum(al);
   be = wave_sum(be);
   ga = wave_sum(ga);
-  if (!(fabs(ga) > tol * sqrt(al * be)) || ga == 0.0) return;
+  if (!(fabs(ga) > eps * sqrt((double)r) * sqrt(al * be)) || ga == 0.0) return;
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
@@ -273,14 +280,15 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
   const int64_t npairs = (int64_t)pairs.size();
   const unsigned grid = (unsigned)std::max<int64_t>(1, (npairs + 3) / 4);
   std::vector<int32_t> flags(nb, 0);
-  for (int sweep = 0; sweep < 60 && npairs > 0 && e == hipSuccess; ++sweep) {
+  bool converged = npairs == 0;
+  for (int sweep = 0; sweep < SVD_MAX_SWEEPS && !converged && e == hipSuccess; ++sweep) {
     svd_clear_kernel<<<1, 256, 0, s>>>(dflags, nb);
     for (int rd = 0; rd < max_rounds; ++rd)
-      svd_round_kernel<<<grid, 256, 0, s>>>(dblocks, dpairs, npairs, rd, work, dflags, 1e-15);
+      svd_round_kernel<<<grid, 256, 0, s>>>(dblocks, dpairs, npairs, rd, work, dflags, 2.220446049250313e-16);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), dflags, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess && std::all_of(flags.begin(), flags.end(), [](int32_t f) { return f == 0; })) break;
+    if (e == hipSuccess) converged = std::all_of(flags.begin(), flags.end(), [](int32_t f) { return f == 0; });
   }
   if (e == hipSuccess) {
     svd_finish_kernel<<<nb, 256, 0, s>>>(dblocks, work, dsig);
@@ -361,5 +369,8 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) return fail(DMRG_EHIP, std::string("svd_truncate: ") + hipGetErrorString(e));
+  if (!converged)
+    return fail(DMRG_ENOCONV, "svd_truncate: Jacobi sweeps still rotating after " +
+                                  std::to_string(SVD_MAX_SWEEPS) + " sweeps (outputs written, not converged)");
   return DMRG_OK;
 }

@@ -216,8 +216,9 @@ class HeffApply(torch.autograd.Function):
         if left_pool.data_ptr() != heff.left_pool.data_ptr() or right_pool.data_ptr() != heff.right_pool.data_ptr():
             raise ValueError("pools must be the tensors the Heff plan was built on")
         ctx.heff = heff
-        ctx.save_for_backward(psi)
-        return heff.apply(psi.contiguous())
+        psi_c = psi.contiguous()
+        ctx.save_for_backward(psi_c)
+        return heff.apply(psi_c)
 
     @staticmethod
     def backward(ctx, ybar):
@@ -248,7 +249,7 @@ def davidson(heff: Heff, psi, tol=1e-8, max_iter=200, max_subspace=24, restart_k
         check(st)
     return dict(energy=res.energy, residual=res.residual, iters=res.iters, matvecs=res.matvecs,
                 converged=bool(res.converged), tail_iters=res.tail_iters, split_iters=res.split_iters,
-                split_residual=res.split_residual, status=st)
+                split_residual=res.split_residual, split_energy=res.split_energy, status=st)
 
 
 def svd_truncate(ctx: Context, Lq, Ld, Rq, Rd, Q, psi, max_keep, cutoff=0.0):

@@ -4,9 +4,10 @@ the benchmark), one matvec in the benchmark's launch configuration (default
 tile rule and workspace), checked on sampled entries against the oracle.
 
 A whole output block is out of the oracle's reach at these sizes, so the
-oracle computes single entries by the same definition (heff_entries): for a
-few rows and columns of the largest, a middle and the smallest wavefunction
-block (first, last and interior indices, so edge tiles are covered).  Each
+oracle computes single entries by the same definition: the first and last
+row and column of EVERY output block (so every block's sum, its K-cut parts
+and its edge tiles are looked at), plus interior rows and columns of the
+largest, a middle and the smallest block.  Each
 entry must agree to 1e-12 times the sum of the absolute values of the
 products that enter it (the scale of its FP64 rounding error).  The split
 and FP32-operand matvecs are checked against the FP64 one norm-wise (their
@@ -30,7 +31,7 @@ def _sample(n, k=3):
 
 @pytest.mark.parametrize("name", ["cas63_58_d4096", "cas113_76_d8192"])
 def test_whole_size_sampled_entries(name):
-    from oracle.heff import heff_entries, layout_of
+    from oracle.heff import heff_entries_blocks, layout_of
     from paper_2407_07411_amd import heff as H
     from synth.problem import WORKLOADS, make_problem
 
@@ -66,17 +67,26 @@ def test_whole_size_sampled_entries(name):
         del h, ctx
         lay = layout_of(prob)
         order = sorted(lay.partner, key=lambda a: int(lay.Ld[a]) * int(lay.Rd[lay.partner[a]]))
+        samples = {}
+        for b in lay.partner:
+            nr, nc = int(lay.Ld[b]), int(lay.Rd[lay.partner[b]])
+            samples[b] = (sorted({0, nr - 1}), sorted({0, nc - 1}))
         for b in (order[-1], order[len(order) // 2], order[0]):
             nr, nc = int(lay.Ld[b]), int(lay.Rd[lay.partner[b]])
-            rows, cols = _sample(nr), _sample(nc)
-            val, mag = heff_entries(prob, b, rows, cols)
-            got = lay.block(y64, b)[np.ix_(rows, cols)]
-            err = np.abs(got - val)
-            print(name, "block", b, (nr, nc), "max err", err.max(), "max scale", mag.max(), flush=True)
-            assert np.all(err <= 1e-12 * mag + 1e-300)
+            samples[b] = (_sample(nr), _sample(nc))
+        print(name, "sampling", len(samples), "output blocks", flush=True)
+        got = heff_entries_blocks(prob, samples)
+        worst = 0.0
+        for b, (rows, cols) in samples.items():
+            val, mag = got[b]
+            ent = lay.block(y64, b)[np.ix_(rows, cols)]
+            err = np.abs(ent - val)
+            worst = max(worst, float((err / (mag + 1e-300)).max()))
+            assert np.all(err <= 1e-12 * mag + 1e-300), (b, err.max(), mag.max())
             for yr in (y16, y32):
-                got16 = lay.block(yr, b)[np.ix_(rows, cols)]
-                assert np.all(np.abs(got16 - val) <= SPLIT_TOL * mag + 1e-300)
+                ent_r = lay.block(yr, b)[np.ix_(rows, cols)]
+                assert np.all(np.abs(ent_r - val) <= SPLIT_TOL * mag + 1e-300), b
+        print(name, "worst FP64 entry error / product scale", worst, flush=True)
     finally:
         del prob
         gc.collect()

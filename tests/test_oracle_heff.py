@@ -259,3 +259,28 @@ def test_sampled_entries_equal_kron_assembly(seed, D, two_sz):
         ref = lay.block(y, b)[np.ix_(rows, cols)]
         assert np.abs(val - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
         assert np.all(mag >= np.abs(val) - 1e-15)
+
+
+@pytest.mark.parametrize("one_sided_hc", [False, True])
+def test_sampled_blocks_equal_kron_assembly(one_sided_hc):
+    """heff_entries_blocks (every output block of a whole-size problem in one
+    pass) against the Kronecker assembly and against heff_entries."""
+    from oracle.heff import heff_entries, heff_entries_blocks
+    prob = tiny_problem(seed=6, D=7, two_sz=0, pairs=3)
+    if one_sided_hc:
+        prob = with_one_sided_hc(prob, seed=6)
+    lay = layout_of(prob)
+    y = kron_dense(prob) @ prob.psi.numpy()
+    samples = {}
+    for b in lay.partner:
+        nr, nc = int(lay.Ld[b]), int(lay.Rd[lay.partner[b]])
+        samples[b] = (sorted({0, nr - 1}), sorted({0, nc // 2, nc - 1}))
+    got = heff_entries_blocks(prob, samples)
+    assert set(got) == set(samples)
+    for b, (rows, cols) in samples.items():
+        val, mag = got[b]
+        ref = lay.block(y, b)[np.ix_(rows, cols)]
+        assert np.abs(val - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+        v1, m1 = heff_entries(prob, b, rows, cols)
+        assert np.allclose(val, v1, rtol=0, atol=1e-13 * max(1.0, np.abs(v1).max()))
+        assert np.allclose(mag, m1, rtol=1e-13, atol=0)
