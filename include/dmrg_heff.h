@@ -267,6 +267,22 @@ dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, co
                               const double* psi, int64_t max_keep, double cutoff,
                               int64_t* kept_dim, double* U, int64_t u_cap, double* S,
                               int64_t s_cap, double* Vt, int64_t vt_cap, double* trunc_err);
+/* For callers that cannot allocate device memory (code under hipGraph capture
+ * of its own, serving loops, harnesses that forbid hipMalloc): the same
+ * truncation, arguments and results as dmrg_svd_truncate, with every device
+ * temporary (working copies of the blocks and their right factors, tables,
+ * singular values, flags) taken from one 64 MiB scratch array that each device
+ * holds until the process ends.  Calls no hipMalloc or hipFree.  The
+ * temporaries need about 8 * (sum over blocks of r*c + c*c + c) bytes (r, c the
+ * longer and shorter block side) plus small tables; larger inputs return
+ * DMRG_ENOMEM with the needed size.  All calls on one device share the array:
+ * calls that overlap in time on one device (other threads, other streams)
+ * race and must be serialised by the caller.  Synchronises. */
+dmrg_status dmrg_svd_truncate_noalloc(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
+                                      const int32_t Q[2], const double* psi, int64_t max_keep,
+                                      double cutoff, int64_t* kept_dim, double* U, int64_t u_cap,
+                                      double* S, int64_t s_cap, double* Vt, int64_t vt_cap,
+                                      double* trunc_err);
 
 /* ---- operator blocks and the two-site sweep -------------------------------- */
 /* The ab initio Hamiltonian H = sum h_pq a+_ps a_qs + 1/2 sum V_pqrs

@@ -80,6 +80,9 @@ SIGNATURES = {
     "dmrg_svd_truncate": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_void_p, c_int64, c_double,
                                   POINTER(c_int64), c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                   POINTER(c_double)]),
+    "dmrg_svd_truncate_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_void_p, c_int64, c_double,
+                                  POINTER(c_int64), c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                  POINTER(c_double)]),
 }
 
 _lib = None

@@ -400,6 +400,7 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx_t* out) {
   DMRG_HIP(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(DMRG_EINVAL, "ctx_create: bad device ordinal");
   DMRG_HIP(hipSetDevice(device));
+  if (dmrg_status st = svd_scratch_init(device); st != DMRG_OK) return st;
   auto* c = new (std::nothrow) dmrg_ctx_s{device, (hipStream_t)hip_stream};
   if (!c) return fail(DMRG_ENOMEM, "ctx_create: out of host memory");
   *out = c;

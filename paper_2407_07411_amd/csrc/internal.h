@@ -164,6 +164,10 @@ struct DiagBlock {
   int64_t off;
   int32_t dl, dr, item0, nitem;
 };
+// Looks up the device address of the allocation-free SVD's scratch array on
+// `device` (current) once; dmrg_ctx_create calls it.
+dmrg_status svd_scratch_init(int device);
+
 dmrg_status launch_diag(const DiagBlock* blocks, int nblocks, const DiagItem* items,
                         const double* lpool, const double* rpool, double* out, int64_t max_elems,
                         hipStream_t s);

@@ -14,6 +14,8 @@
 // kept factors.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -199,13 +201,42 @@ __global__ __launch_bounds__(256) void svd_pack_kernel(const SvdBlock* __restric
 
 using namespace dmrg;
 
-extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
-                                         const int32_t Q[2], const double* psi, int64_t max_keep,
-                                         double cutoff, int64_t* kept_dim, double* U, int64_t u_cap,
-                                         double* S, int64_t s_cap, double* Vt, int64_t vt_cap,
-                                         double* trunc_err) {
+namespace dmrg {
+
+// Device temporaries of one truncation, carved out of one arena (aligned to
+// 256 bytes each): the working copies B and V, the block and pair tables,
+// the singular values, the rotation flags, the pack table and the kept
+// permutation (at most one entry per singular value).
+struct SvdArena {
+  size_t work, blocks, sig, pairs, flags, packs, perm, total;
+};
+
+SvdArena svd_arena(int64_t woff, int nb, int64_t soff, int64_t npairs) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  SvdArena a{};
+  size_t o = 0;
+  a.work = o;   o += up(std::max<int64_t>(woff, 1) * sizeof(double));
+  a.blocks = o; o += up((size_t)nb * sizeof(SvdBlock));
+  a.sig = o;    o += up(std::max<int64_t>(soff, 1) * sizeof(double));
+  a.pairs = o;  o += up(std::max<int64_t>(npairs, 1) * sizeof(SvdPair));
+  a.flags = o;  o += up((size_t)nb * sizeof(int32_t));
+  a.packs = o;  o += up((size_t)nb * sizeof(PackBlock));
+  a.perm = o;   o += up(std::max<int64_t>(soff, 1) * sizeof(int32_t));
+  a.total = o;
+  return a;
+}
+
+// The truncation itself.  arena: device memory of at least arena_cap bytes
+// for the temporaries, or NULL to allocate them here (one hipMalloc, freed
+// before returning).
+dmrg_status svd_truncate_impl(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                              const double* psi, int64_t max_keep, double cutoff, int64_t* kept_dim,
+                              double* U, int64_t u_cap, double* S, int64_t s_cap, double* Vt,
+                              int64_t vt_cap, double* trunc_err, char* arena, size_t arena_cap,
+                              const char* who) {
+  const std::string name(who);
   if (!ctx || !L || !R || !Q || !psi || !kept_dim || !trunc_err || max_keep < 0 || !(cutoff >= 0.0))
-    return fail(DMRG_EINVAL, "svd_truncate: bad arguments");
+    return fail(DMRG_EINVAL, name + ": bad arguments");
   hipStream_t s = ctx->stream;
   const int nL = (int)L->dim.size();
   std::vector<SvdBlock> blocks;
@@ -232,27 +263,8 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
     blocks.push_back(b);
     sector.push_back(a);
   }
-  if (blocks.empty()) return fail(DMRG_EQN, "svd_truncate: no block has total Q");
+  if (blocks.empty()) return fail(DMRG_EQN, name + ": no block has total Q");
   const int nb = (int)blocks.size();
-  double* work = nullptr;
-  SvdBlock* dblocks = nullptr;
-  double* dsig = nullptr;
-  PackBlock* dpacks = nullptr;
-  int32_t* dperm = nullptr;
-  auto cleanup = [&]() {
-    if (work) (void)hipFree(work);
-    if (dblocks) (void)hipFree(dblocks);
-    if (dsig) (void)hipFree(dsig);
-    if (dpacks) (void)hipFree(dpacks);
-    if (dperm) (void)hipFree(dperm);
-  };
-  if (hipMalloc(&work, std::max<int64_t>(woff, 1) * sizeof(double)) != hipSuccess ||
-      hipMalloc(&dblocks, nb * sizeof(SvdBlock)) != hipSuccess ||
-      hipMalloc(&dsig, std::max<int64_t>(soff, 1) * sizeof(double)) != hipSuccess) {
-    cleanup();
-    return fail(DMRG_ENOMEM, "svd_truncate: device allocation failed");
-  }
-  std::vector<double> sig(soff);
   // flattened (block, pair slot) list; rounds per sweep = the largest block's
   std::vector<SvdPair> pairs;
   int max_rounds = 0;
@@ -262,14 +274,28 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
     for (int pi = 0; pi < m / 2; ++pi) pairs.push_back(SvdPair{i, pi});
     max_rounds = std::max(max_rounds, m - 1);
   }
-  SvdPair* dpairs = nullptr;
-  int32_t* dflags = nullptr;
-  if (hipMalloc(&dpairs, std::max<size_t>(pairs.size(), 1) * sizeof(SvdPair)) != hipSuccess ||
-      hipMalloc(&dflags, nb * sizeof(int32_t)) != hipSuccess) {
-    if (dpairs) (void)hipFree(dpairs);
-    cleanup();
-    return fail(DMRG_ENOMEM, "svd_truncate: device allocation failed");
+  const int64_t npairs = (int64_t)pairs.size();
+  const SvdArena lay = svd_arena(woff, nb, soff, npairs);
+  char* mem = arena;
+  if (arena) {
+    if (lay.total > arena_cap)
+      return fail(DMRG_ENOMEM, name + ": needs " + std::to_string(lay.total) +
+                                   " bytes of device scratch, more than its " +
+                                   std::to_string(arena_cap) + "-byte maximum");
+  } else if (hipMalloc((void**)&mem, lay.total) != hipSuccess) {
+    return fail(DMRG_ENOMEM, name + ": device allocation failed");
   }
+  auto cleanup = [&]() {
+    if (!arena && mem) (void)hipFree(mem);
+  };
+  double* work = (double*)(mem + lay.work);
+  SvdBlock* dblocks = (SvdBlock*)(mem + lay.blocks);
+  double* dsig = (double*)(mem + lay.sig);
+  SvdPair* dpairs = (SvdPair*)(mem + lay.pairs);
+  int32_t* dflags = (int32_t*)(mem + lay.flags);
+  PackBlock* dpacks = (PackBlock*)(mem + lay.packs);
+  int32_t* dperm = (int32_t*)(mem + lay.perm);
+  std::vector<double> sig(soff);
   hipError_t e = hipMemcpyAsync(dblocks, blocks.data(), nb * sizeof(SvdBlock), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !pairs.empty())
     e = hipMemcpyAsync(dpairs, pairs.data(), pairs.size() * sizeof(SvdPair), hipMemcpyHostToDevice, s);
@@ -277,7 +303,6 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
     svd_load_kernel<<<nb, 256, 0, s>>>(dblocks, psi, work);
     e = hipGetLastError();
   }
-  const int64_t npairs = (int64_t)pairs.size();
   const unsigned grid = (unsigned)std::max<int64_t>(1, (npairs + 3) / 4);
   std::vector<int32_t> flags(nb, 0);
   bool converged = npairs == 0;
@@ -294,13 +319,11 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
     svd_finish_kernel<<<nb, 256, 0, s>>>(dblocks, work, dsig);
     e = hipGetLastError();
   }
-  (void)hipFree(dpairs);
-  (void)hipFree(dflags);
   if (e == hipSuccess) e = hipMemcpyAsync(sig.data(), dsig, soff * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     cleanup();
-    return fail(DMRG_EHIP, std::string("svd_truncate: ") + hipGetErrorString(e));
+    return fail(DMRG_EHIP, name + ": " + hipGetErrorString(e));
   }
   // per block: descending order; globally: (sigma desc, sector asc, position asc)
   std::vector<std::vector<int32_t>> order(nb);
@@ -352,12 +375,7 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
   }
   if ((uo > 0 && (!U || uo > u_cap)) || (so > 0 && (!S || so > s_cap)) || (vo > 0 && (!Vt || vo > vt_cap))) {
     cleanup();
-    return fail(DMRG_EINVAL, "svd_truncate: output buffers too small");
-  }
-  if (hipMalloc(&dpacks, nb * sizeof(PackBlock)) != hipSuccess ||
-      hipMalloc(&dperm, std::max<size_t>(perm.size(), 1) * sizeof(int32_t)) != hipSuccess) {
-    cleanup();
-    return fail(DMRG_ENOMEM, "svd_truncate: device allocation failed");
+    return fail(DMRG_EINVAL, name + ": output buffers too small");
   }
   e = hipMemcpyAsync(dpacks, packs.data(), nb * sizeof(PackBlock), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !perm.empty())
@@ -368,9 +386,69 @@ extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_ba
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
-  if (e != hipSuccess) return fail(DMRG_EHIP, std::string("svd_truncate: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(DMRG_EHIP, name + ": " + hipGetErrorString(e));
   if (!converged)
-    return fail(DMRG_ENOCONV, "svd_truncate: Jacobi sweeps still rotating after " +
+    return fail(DMRG_ENOCONV, name + ": Jacobi sweeps still rotating after " +
                                   std::to_string(SVD_MAX_SWEEPS) + " sweeps (outputs written, not converged)");
   return DMRG_OK;
+}
+
+}  // namespace dmrg
+
+extern "C" dmrg_status dmrg_svd_truncate(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
+                                         const int32_t Q[2], const double* psi, int64_t max_keep,
+                                         double cutoff, int64_t* kept_dim, double* U, int64_t u_cap,
+                                         double* S, int64_t s_cap, double* Vt, int64_t vt_cap,
+                                         double* trunc_err) {
+  return svd_truncate_impl(ctx, L, R, Q, psi, max_keep, cutoff, kept_dim, U, u_cap, S, s_cap, Vt,
+                           vt_cap, trunc_err, nullptr, 0, "svd_truncate");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free truncation.  Its temporaries live in `scratch`, a
+// file-scope device array that every device the library runs on holds (one
+// copy each) until the process ends.  In host code the array's name is not a
+// device address: its per-device address comes from hipGetSymbolAddress,
+// taken once per device when a context is created on it, and only that
+// pointer is handed to kernels and copies.
+namespace dmrg {
+
+constexpr size_t SVD_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) char scratch[SVD_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[MAX_DEVICES] = {};
+}  // namespace
+
+// Called by dmrg_ctx_create with `device` current.
+dmrg_status svd_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(DMRG_ENOTSUP, "svd scratch: device ordinal too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return DMRG_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(DMRG_EHIP, std::string("svd scratch: hipGetSymbolAddress: ") + hipGetErrorString(e));
+  g_scratch[device] = (char*)ptr;
+  return DMRG_OK;
+}
+
+}  // namespace dmrg
+
+extern "C" dmrg_status dmrg_svd_truncate_noalloc(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
+                                                 const int32_t Q[2], const double* psi,
+                                                 int64_t max_keep, double cutoff, int64_t* kept_dim,
+                                                 double* U, int64_t u_cap, double* S, int64_t s_cap,
+                                                 double* Vt, int64_t vt_cap, double* trunc_err) {
+  if (!ctx) return fail(DMRG_EINVAL, "svd_truncate_noalloc: bad arguments");
+  char* mem = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < MAX_DEVICES) mem = g_scratch[ctx->device];
+  }
+  if (!mem) return fail(DMRG_EINVAL, "svd_truncate_noalloc: no scratch address for the context's device");
+  return svd_truncate_impl(ctx, L, R, Q, psi, max_keep, cutoff, kept_dim, U, u_cap, S, s_cap, Vt,
+                           vt_cap, trunc_err, mem, SVD_SCRATCH_BYTES, "svd_truncate_noalloc");
 }

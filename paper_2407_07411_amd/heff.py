@@ -252,9 +252,12 @@ def davidson(heff: Heff, psi, tol=1e-8, max_iter=200, max_subspace=24, restart_k
                 split_residual=res.split_residual, split_energy=res.split_energy, status=st)
 
 
-def svd_truncate(ctx: Context, Lq, Ld, Rq, Rd, Q, psi, max_keep, cutoff=0.0):
+def svd_truncate(ctx: Context, Lq, Ld, Rq, Rd, Q, psi, max_keep, cutoff=0.0, out=None, noalloc=False):
     """Block-wise SVD of psi with global truncation.  Returns (kept_dim,
-    U, S, Vt, trunc_err) with the factors packed per left sector."""
+    U, S, Vt, trunc_err) with the factors packed per left sector.  out: an
+    optional (U, S, Vt) of device buffers to write into.  noalloc: run the
+    library's allocation-free variant (temporaries in its per-device scratch
+    array)."""
     L, R = Basis(ctx, Lq, Ld), Basis(ctx, Rq, Rd)
     _dev_f64(psi, "psi")
     Ld, Rd = L.dim, R.dim
@@ -272,14 +275,18 @@ def svd_truncate(ctx: Context, Lq, Ld, Rq, Rd, Q, psi, max_keep, cutoff=0.0):
         scap += k
         vcap += k * Rd[c]
     dev = ctx.device
-    U = torch.empty(max(1, ucap), dtype=torch.float64, device=dev)
-    S = torch.empty(max(1, scap), dtype=torch.float64, device=dev)
-    Vt = torch.empty(max(1, vcap), dtype=torch.float64, device=dev)
+    if out is None:
+        U = torch.empty(max(1, ucap), dtype=torch.float64, device=dev)
+        S = torch.empty(max(1, scap), dtype=torch.float64, device=dev)
+        Vt = torch.empty(max(1, vcap), dtype=torch.float64, device=dev)
+    else:
+        U, S, Vt = (_dev_f64(t, n) for t, n in zip(out, ("U", "S", "Vt")))
     kept = np.zeros(len(Ld), dtype=np.int64)
     err = c_double()
     q = (c_int32 * 2)(int(Q[0]), int(Q[1]))
     ctx.sync_stream()
-    check(lib().dmrg_svd_truncate(ctx.h, L.h, R.h, q, _ptr(psi), int(max_keep), float(cutoff),
+    fn = lib().dmrg_svd_truncate_noalloc if noalloc else lib().dmrg_svd_truncate
+    check(fn(ctx.h, L.h, R.h, q, _ptr(psi), int(max_keep), float(cutoff),
                                   kept.ctypes.data_as(ctypes.POINTER(c_int64)), _ptr(U), U.numel(), _ptr(S),
                                   S.numel(), _ptr(Vt), Vt.numel(), byref(err)))
     return kept, U, S, Vt, err.value
