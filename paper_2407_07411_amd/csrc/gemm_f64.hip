@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "tile_dma.h"
 
 namespace dmrg {
 
@@ -255,6 +256,19 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
       }
 }
 
+// The same grouped GEMM with operands loaded straight into LDS (tile_dma.h).
+template <int BM, int BN, int WGM, int WGN, int NST>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 && NST == 2 ? 6 : 1))) void gemm_f64_dma_kernel(
+    Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
+    const Tile* __restrict__ tiles, int64_t ntiles) {
+  __shared__ __align__(16) double lds[NST * (BM + BN) * dma::BK];
+  const int64_t lt = xcd_remap(blockIdx.x, ntiles);
+  const Tile t = tiles[lt];
+  const Prob p = probs[t.prob];
+  dma::tile_f64<BM, BN, WGM, WGN, NST>(bases, p, segs, t.tm, t.tn, (int)(blockIdx.x & 3), lds);
+}
+
 // FP32-operand form of the same grouped GEMM: operand values are rounded to
 // FP32 while they are staged into LDS and multiplied on the FP32 matrix cores
 // (v_mfma_f32_16x16x4f32: twice the FP64 rate); the FP32 partial, times the
@@ -430,12 +444,20 @@ dmrg_status launch_gemm_f32(const Launch& l, const Bases& b, const Prob* probs, 
 }
 
 int cfg_bm(int cfg) {
-  return cfg == CFG_F64_32                                ? 32
-         : cfg == CFG_F64_64 || cfg == CFG_F64_64x128     ? 64
-         : cfg == CFG_F64_256x128                         ? 256
-                                                          : 128;
+  switch (cfg) {
+    case CFG_F64_32: case CFG_D_32x32: return 32;
+    case CFG_F64_64: case CFG_F64_64x128: case CFG_D_64x128: case CFG_D_64x128S3: case CFG_D_64x64: return 64;
+    case CFG_F64_256x128: return 256;
+    default: return 128;
+  }
 }
-int cfg_bn(int cfg) { return cfg == CFG_F64_32 ? 32 : cfg == CFG_F64_64 ? 64 : 128; }
+int cfg_bn(int cfg) {
+  switch (cfg) {
+    case CFG_F64_32: case CFG_D_32x32: return 32;
+    case CFG_F64_64: case CFG_D_64x64: return 64;
+    default: return 128;
+  }
+}
 
 dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                         const Tile* tiles, hipStream_t s) {
@@ -462,6 +484,21 @@ dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, cons
       break;
     case CFG_F64_64x128:
       gemm_f64_kernel<64, 128, 16, 2, 4><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_D_64x128:
+      gemm_f64_dma_kernel<64, 128, 2, 4, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_D_64x128S3:
+      gemm_f64_dma_kernel<64, 128, 2, 4, 3><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_D_128x128:
+      gemm_f64_dma_kernel<128, 128, 4, 2, 2><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_D_64x64:
+      gemm_f64_dma_kernel<64, 64, 2, 2, 2><<<grid, 256, 0, s>>>(b, probs, segs, t, l.ntiles);
+      break;
+    case CFG_D_32x32:
+      gemm_f64_dma_kernel<32, 32, 1, 1, 2><<<grid, 64, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
     default:
       return fail(DMRG_EINVAL, "unknown tile configuration");

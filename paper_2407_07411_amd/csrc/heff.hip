@@ -251,6 +251,26 @@ int choose_cfg(int M, int N, bool split) {
   return CFG_F64_32;
 }
 
+// FP64 programs: DMRG_HEFF_DMA selects the LDS-load kernels for the shapes
+// above (1: 2-deep ring, 2: 3-deep ring for 64x128, 3: 128x128 for large
+// problems); 0 keeps the register-staged kernels.
+int dma_mode() {
+  const char* s = std::getenv("DMRG_HEFF_DMA");
+  return s ? std::atoi(s) : 0;
+}
+int to_dma(int cfg, int M, int N) {
+  const int mode = dma_mode();
+  if (mode <= 0) return cfg;
+  switch (cfg) {
+    case CFG_F64_64x128:
+      if (mode == 3 && M >= 96 && N >= 96) return CFG_D_128x128;
+      return mode == 2 ? CFG_D_64x128S3 : CFG_D_64x128;
+    case CFG_F64_64: return CFG_D_64x64;
+    case CFG_F64_32: return CFG_D_32x32;
+    default: return cfg;
+  }
+}
+
 // Appends the tiles of `probs[first..)` grouped by tile configuration, one
 // launch per configuration.
 void ProgramBuilder::close_phase() {
@@ -320,6 +340,7 @@ void ProgramBuilder::close_phase() {
       if (kt <= 256) cfg = CFG_F64_64;
     }
     if (cfg < 0) cfg = choose_cfg(p.M, p.N, split);
+    if (!split && !reduced && cfg_override < 0) cfg = to_dma(cfg, p.M, p.N);
     prog.probs[pi].pad0 = (uint8_t)phase_id;
     int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
     int tm = (p.M + bm - 1) / bm, tn = (p.N + bn - 1) / bn;

@@ -40,6 +40,9 @@ enum BufId : uint8_t {
 };
 struct Bases {
   double* p[BUF_COUNT];
+  // Length of each buffer in doubles (bounds the staged loads of the kernels
+  // that fetch whole K tiles).
+  int64_t len[BUF_COUNT] = {};
   // Bit b set: buffer b holds pre-split operands, one 64-bit word per value
   // with its three BF16 slices in bits 0-15, 16-31 and 32-47 (bits 48-63
   // zero).  Only the split-precision kernel reads or writes such buffers.
@@ -81,8 +84,16 @@ enum TileCfg : int32_t {
   CFG_F64_128W8 = 3,   // 128x128 tile, 8 waves (two per SIMD)
   CFG_F64_256x128 = 4, // 256x128 tile, 8 waves
   CFG_F64_64x128 = 5,  // 64x128 tile, 8 waves of 32x32 (six waves per SIMD fit)
-  CFG_F64_COUNT = 6
+  // FP64 tiles with operands loaded straight into LDS (tile_dma.h)
+  CFG_D_64x128 = 6,    // 64x128, 8 waves of 32x32, 2-deep K-tile ring
+  CFG_D_64x128S3 = 7,  // 64x128, 8 waves of 32x32, 3-deep ring
+  CFG_D_128x128 = 8,   // 128x128, 8 waves of 32x64, 2-deep ring
+  CFG_D_64x64 = 9,     // 64x64, 4 waves of 32x32, 2-deep ring
+  CFG_D_32x32 = 10,    // 32x32, 1 wave, 2-deep ring
+  CFG_F64_COUNT = 11
 };
+// Shapes the split and FP32-operand kernels are built for.
+constexpr int CFG_REDUCED_COUNT = 6;
 int cfg_bm(int cfg);
 int cfg_bn(int cfg);
 

@@ -49,6 +49,7 @@ struct ProgramBuilder {
   int cfg_override = -1;
   int phase_id = 0;                 // 0: intermediates, 1: sums into the outputs
   bool split = false;               // tile rule of the split-precision kernels
+  bool reduced = false;             // a split or FP32-operand program (no LDS-load shapes)
   int32_t phase_seq = 0;            // phases closed so far
   const TuneTable* tune = nullptr;
   int32_t add_prob(uint8_t cbuf, int64_t coff, int M, int N, int ldc, bool beta);

@@ -224,6 +224,7 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
   pb.split = which == 1;
+  pb.reduced = which != 0;
   pb.tune = &h->tune[which];
   const int nb = (int)h->blocks.size();
   const size_t ni = h->items.size();
@@ -331,6 +332,7 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
 dmrg_status build_adjoint(dmrg_heff_s* h, int cfg_override) {
   ProgramBuilder pb;
   pb.cfg_override = cfg_override;
+  pb.reduced = false;
   // built-in tile rule: the forward program's tuned table was measured on
   // other shapes (gradient blocks are operator-shaped with short K) and made
   // the adjoint slower
@@ -521,6 +523,11 @@ Bases fwd_bases(dmrg_heff_s* h, const double* psi, double* y) {
   b.p[BUF_RPOOL] = const_cast<double*>(h->rpool);
   b.p[BUF_WORK] = h->work;
   b.p[BUF_PART] = h->part;
+  b.len[BUF_PSI] = b.len[BUF_Y] = h->size;
+  b.len[BUF_LPOOL] = h->llen;
+  b.len[BUF_RPOOL] = h->rlen;
+  b.len[BUF_WORK] = h->work_elems;
+  b.len[BUF_PART] = h->part_elems;
   if (h->prec == DMRG_SPLIT_BF16X3 && h->split_pack) {
     b.p[BUF_PSI] = h->psi_pk;
     b.packed = (1u << BUF_PSI) | (1u << BUF_WORK);
@@ -837,6 +844,14 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
   b.p[BUF_GL] = left_pool_bar;
   b.p[BUF_GR] = right_pool_bar;
   b.p[BUF_PART] = h->adj_part;
+  b.len[BUF_PSI] = b.len[BUF_YBAR] = h->size;
+  b.len[BUF_Y] = psibar ? h->size : 0;
+  b.len[BUF_LPOOL] = h->llen;
+  b.len[BUF_RPOOL] = h->rlen;
+  b.len[BUF_WORK] = h->adj_work_elems;
+  b.len[BUF_GL] = left_pool_bar ? h->llen : 0;
+  b.len[BUF_GR] = right_pool_bar ? h->rlen : 0;
+  b.len[BUF_PART] = std::max<int64_t>(h->adj.part_elems, 1);
   return h->adj.run(b, h->ctx->stream, DMRG_FP64);
 }
 
@@ -884,7 +899,8 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
   for (auto& kv : groups) {
     float best = 0.f;
     int best_cfg = -1;
-    for (int cfg = 0; cfg < CFG_F64_COUNT; ++cfg) {
+    const int ncfg = h->prec == DMRG_FP64 ? CFG_F64_COUNT : CFG_REDUCED_COUNT;
+    for (int cfg = 0; cfg < ncfg; ++cfg) {
       // the split kernel's 256x128 shape spills registers: not a candidate
       if (h->prec == DMRG_SPLIT_BF16X3 && cfg == CFG_F64_256x128) continue;
       const int bm = cfg_bm(cfg), bn = cfg_bn(cfg);
