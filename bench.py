@@ -35,7 +35,10 @@ KERNEL_NAMES = {0: "gemm_f64_kernel<32,32,16,1,1>", 1: "gemm_f64_kernel<64,64,16
                 17: "gemm_split_kernel<64,64,2,2>", 18: "gemm_split_kernel<128,128,2,2>",
                 19: "gemm_split_kernel<128,128,4,4,1,64>", 20: "gemm_split_kernel<256,128,4,4>",
                 21: "gemm_split_kernel<64,128,2,4>",
-                32: "reduce_kernel",
+                6: "gemm_f64_dma_kernel<64,128,2,4,2>", 7: "gemm_f64_dma_kernel<64,128,2,4,3>",
+                8: "gemm_f64_dma_kernel<128,128,4,2,2>", 9: "gemm_f64_dma_kernel<64,64,2,2,2>",
+                10: "gemm_f64_dma_kernel<32,32,1,1,2>",
+                32: "reduce_kernel", 64: "persist_f64_kernel",
                 48: "gemm_f32_kernel<32,32,32,1,1>", 49: "gemm_f32_kernel<64,64,32,2,2>",
                 50: "gemm_f32_kernel<128,128,16,2,2>", 51: "gemm_f32_kernel<128,128,32,4,2>",
                 52: "gemm_f32_kernel<256,128,16,4,2>", 53: "gemm_f32_kernel<64,128,32,2,4>"}
@@ -90,7 +93,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the Davidson-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tune", action="store_true", help="run the tile-shape autotuner before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (tile shapes per size class, per-phase or persistent launch)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the off-path measurements (SVD truncation, adjoint at L=24)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -144,10 +148,31 @@ def main():
             f"({plan_s:.1f} s)")
         x = prob.psi.clone()
         y = torch.empty_like(x)
-        if args.tune:
+        # the two launch forms of the FP64 matvec (bit-identical results)
+        forms = {}
+        for pers in (False, True):
+            h.set_persistent(pers)
+            h.apply(x, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(2):
+                h.apply(x, y)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            forms["persistent" if pers else "per_phase"] = e0.elapsed_time(e1) / 2
+        h.check()
+        h.set_persistent(False)
+        log(f"untuned matvec: per-phase launches {forms['per_phase']:.1f} ms, one persistent launch "
+            f"{forms['persistent']:.1f} ms")
+        tune_s = None
+        if not args.no_tune:
             t0 = time.time()
             h.autotune(x, y, reps=2)
-            log(f"autotuned tile shapes ({time.time()-t0:.1f} s)")
+            tune_s = time.time() - t0
+            log(f"autotuned ({tune_s:.1f} s)")
+        kid0, _ = h.launches()
+        form = "persistent" if len(kid0) == 1 and int(kid0[0]) == 64 else "per_phase"
+        log(f"matvec form: {form}")
 
         # ---- matvec alone (FP64): warm-up, then HIP events on this stream
         for _ in range(2):
@@ -223,7 +248,9 @@ def main():
         ev[1].record(stream)
         torch.cuda.synchronize()
         diag_ms = ev[0].elapsed_time(ev[1])
-        extra = dict(plan_seconds=round(plan_s, 3), diag_ms=round(diag_ms, 3),
+        extra = dict(plan_seconds=round(plan_s, 3), tune_seconds=None if tune_s is None else round(tune_s, 3),
+                     matvec_form=form, untuned_matvec_ms=dict((k, round(v, 3)) for k, v in forms.items()),
+                     diag_ms=round(diag_ms, 3),
                      matvec_ms_fp64=round(mv_ms, 3), matvec_tflops_fp64=round(flops / mv_ms / 1e9, 3),
                      davidson_iter_ms_fp64=round(step_ms, 3), alg_tflop_per_matvec=round(flops / 1e12, 4),
                      alg_intensity_flop_per_byte=round(flops / alg_bytes, 1))

@@ -169,6 +169,23 @@ int64_t dmrg_heff_workspace_bytes(dmrg_heff_t h);
  * later applies with the same pointers (1) or launch eagerly (0). */
 dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable);
 
+/* Persistent single-launch matvec (FP64): every phase of the product (the
+ * intermediates of each workspace wave, the long-K output sums, the ordered
+ * reductions of cut sums) runs in ONE kernel launch whose workgroups take
+ * 64x128 output tiles from per-phase, per-XCD queues and wait (bounded) for
+ * the previous phase to complete; consecutive tiles of a workgroup are
+ * pipelined (the next tile's first K tile loads during the current tile's
+ * last).  Results are bit-identical to the per-phase launches.  enable = 1
+ * builds the task tables (device memory, synchronous) and selects this form
+ * for FP64 applies (and Davidson); 0 returns to per-phase launches.  The
+ * split and FP32-operand precisions always use per-phase launches.  The
+ * environment variable DMRG_HEFF_PERSIST=1 enables it at creation. */
+dmrg_status dmrg_heff_set_persistent(dmrg_heff_t h, int32_t enable);
+/* Synchronises the context stream and reports whether a persistent launch
+ * since the last check gave up waiting for an earlier phase (DMRG_EHIP: its
+ * results are not valid; the flag is cleared).  DMRG_OK otherwise. */
+dmrg_status dmrg_heff_check(dmrg_heff_t h);
+
 /* Autotuner: times every tile shape (the kernel ids of dmrg_heff_launches;
  * the split kernels skip 256x128) on the plan's
  * own problems, grouped by phase (intermediates / output sums) and by the
@@ -176,7 +193,9 @@ dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable);
  * shape per group and rebuilds the plan with it.  The timing runs the
  * current precision's kernels on the context stream with psi and y (device
  * double[size]; y and the workspace are overwritten).  reps >= 1 timed
- * launches per candidate.  The adjoint keeps the built-in rule.
+ * launches per candidate.  The adjoint keeps the built-in rule.  For FP64
+ * it then times the rebuilt matvec as per-phase launches and as the single
+ * persistent launch (dmrg_heff_set_persistent) and keeps the faster form.
  * Synchronises. */
 dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps);
 

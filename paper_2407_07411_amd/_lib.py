@@ -53,6 +53,8 @@ SIGNATURES = {
                                  c_void_p, c_int64, c_void_p, c_int64, c_int, POINTER(c_void_p)]),
     "dmrg_heff_destroy": (None, [c_void_p]),
     "dmrg_heff_set_precision": (c_int, [c_void_p, c_int]),
+    "dmrg_heff_set_persistent": (c_int, [c_void_p, c_int32]),
+    "dmrg_heff_check": (c_int, [c_void_p]),
     "dmrg_heff_flops": (c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
     "dmrg_heff_size": (c_int64, [c_void_p]),
     "dmrg_heff_apply": (c_int, [c_void_p, c_void_p, c_void_p]),

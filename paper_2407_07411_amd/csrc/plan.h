@@ -57,6 +57,35 @@ struct ProgramBuilder {
   void close_phase();
 };
 
+// One task of the persistent matvec: an output tile (prob >= 0; row tile
+// tm, column tile tn & 0x3fff, tile shape tn >> 14) or a chunk of rows of a
+// K-cut reduction (prob = -1 - reduction; chunk tm).
+struct PTask {
+  int32_t prob;
+  int16_t tm;
+  uint16_t tn;
+};
+static_assert(sizeof(PTask) == 8, "PTask layout");
+
+// The persistent form of a FP64 forward program: tasks grouped in phases,
+// each phase split into eight ranges (persist.hip).
+struct Persist {
+  bool built = false;
+  int nph = 0;
+  int grid = 0;
+  std::vector<PTask> tasks;
+  std::vector<int64_t> qstart;  // [nph * 8 + 1] first task of each (phase, range)
+  std::vector<int32_t> ntask;   // [nph] tasks per phase
+  PTask* d_tasks = nullptr;
+  int64_t* d_qstart = nullptr;
+  int32_t* d_ntask = nullptr;
+  int32_t* d_ctl = nullptr;     // heads, completions, exit count, give-up flag
+  dmrg_status build(const Program& P);
+  void release();
+  dmrg_status run(const Bases& b, const Program& P, hipStream_t s, int64_t spin_limit) const;
+  dmrg_status check(hipStream_t s) const;  // synchronises; reports a give-up
+};
+
 dmrg_status heff_apply_eager(struct ::dmrg_heff_s* h, const double* psi, double* y);
 Seg make_seg(uint8_t xbuf, int64_t xoff, int ldx, bool xt, uint8_t zbuf, int64_t zoff, int ldz,
              bool zt, int K, double alpha);
@@ -103,6 +132,10 @@ struct dmrg_heff_s {
   dmrg::DiagItem* d_ditems = nullptr;
   int n_dblocks = 0;
   int64_t max_block_elems = 0;
+  // persistent single-launch form of the FP64 forward program
+  dmrg::Persist pers;
+  int persistent = 0;
+  int64_t spin_limit = 2000000000;  // ticks of the 100 MHz counter (20 s)
   // graph cache for the matvec
   int use_graph = 0;
   const double* g_psi = nullptr;

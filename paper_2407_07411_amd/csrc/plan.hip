@@ -558,7 +558,9 @@ namespace dmrg {
 dmrg_status heff_apply_eager(dmrg_heff_s* h, const double* psi, double* y) {
   const Bases b = fwd_bases(h, psi, y);
   dmrg_status st = fwd_prologue(h, psi, b);
-  return st != DMRG_OK ? st : h->fwd().run(b, h->ctx->stream, h->prec);
+  if (st != DMRG_OK) return st;
+  if (h->persistent && h->prec == DMRG_FP64) return h->pers.run(b, h->fwdp[0], h->ctx->stream, h->spin_limit);
+  return h->fwd().run(b, h->ctx->stream, h->prec);
 }
 }  // namespace dmrg
 
@@ -656,13 +658,22 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
     (void)hipFree(h->part);
     return st;
   }
-  *out = h.release();
+  if (const char* e = std::getenv("DMRG_HEFF_SPIN_TICKS")) h->spin_limit = std::atoll(e);
+  dmrg_heff_s* hp = h.release();
+  if (const char* e = std::getenv("DMRG_HEFF_PERSIST"); e && std::atoi(e) != 0) {
+    if ((st = dmrg_heff_set_persistent(hp, 1)) != DMRG_OK) {
+      dmrg_heff_destroy(hp);
+      return st;
+    }
+  }
+  *out = hp;
   return DMRG_OK;
 }
 
 void dmrg_heff_destroy(dmrg_heff_t h) {
   if (!h) return;
   free_graph(h);
+  h->pers.release();
   for (auto& p : h->fwdp) p.release();
   h->adj.release();
   if (h->work) (void)hipFree(h->work);
@@ -682,6 +693,22 @@ dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec) {
     return fail(DMRG_EINVAL, "set_precision: unknown precision");
   h->prec = prec;
   return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_set_persistent(dmrg_heff_t h, int32_t enable) {
+  if (!h) return fail(DMRG_EINVAL, "set_persistent: h is NULL");
+  if (enable && !h->pers.built) {
+    dmrg_status st = h->pers.build(h->fwdp[0]);
+    if (st != DMRG_OK) return st;
+  }
+  if ((enable != 0) != (h->persistent != 0)) free_graph(h);
+  h->persistent = enable ? 1 : 0;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_check(dmrg_heff_t h) {
+  if (!h) return fail(DMRG_EINVAL, "heff_check: h is NULL");
+  return h->pers.check(h->ctx->stream);
 }
 
 dmrg_status dmrg_heff_flops(dmrg_heff_t h, double* alg_flops, double* alg_bytes) {
@@ -734,6 +761,17 @@ dmrg_status dmrg_heff_apply(dmrg_heff_t h, const double* psi, double* y) {
 dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops) {
   if (!h || !n_launches) return fail(DMRG_EINVAL, "heff_launches: bad arguments");
   const auto& P = h->fwd();
+  if (h->persistent && h->prec == DMRG_FP64) {  // one launch: the persistent kernel
+    *n_launches = 1;
+    if (kernel) kernel[0] = 64;
+    if (flops) {
+      double f = 0.0;
+      for (const Prob& p : P.probs)
+        for (int sg = p.seg0; sg < p.seg0 + p.nseg; ++sg) f += 2.0 * p.M * p.N * P.segs[sg].K;
+      flops[0] = f;
+    }
+    return DMRG_OK;
+  }
   *n_launches = (int64_t)P.launches.size();
   for (size_t i = 0; i < P.launches.size(); ++i) {
     const Launch& l = P.launches[i];
@@ -770,7 +808,12 @@ dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y
   const Bases b = fwd_bases(h, psi, y);
   if (st == DMRG_OK) st = fwd_prologue(h, psi, b);
   if (st == DMRG_OK && hipEventRecord(ev[0], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
-  for (size_t i = 0; i < n && st == DMRG_OK; ++i) {
+  const bool pers = h->persistent && h->prec == DMRG_FP64;
+  if (pers && st == DMRG_OK) {
+    st = h->pers.run(b, P, s, h->spin_limit);
+    if (st == DMRG_OK && hipEventRecord(ev[1], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
+  }
+  for (size_t i = 0; i < n && st == DMRG_OK && !pers; ++i) {
     Launch x = P.launches[i];
     x.split = h->prec;
     st = x.cfg == CFG_REDUCE ? launch_reduce(x, b, P.d_reds, P.d_red_parts, s)
@@ -779,7 +822,7 @@ dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y
       st = fail(DMRG_EHIP, "hipEventRecord failed");
   }
   if (st == DMRG_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(DMRG_EHIP, "hipStreamSynchronize failed");
-  for (size_t i = 0; i < n && st == DMRG_OK; ++i)
+  for (size_t i = 0; i < (pers ? 1 : n) && st == DMRG_OK; ++i)
     if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess)
       st = fail(DMRG_EHIP, "hipEventElapsedTime failed");
   for (auto e : ev)
@@ -899,7 +942,7 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
   for (auto& kv : groups) {
     float best = 0.f;
     int best_cfg = -1;
-    const int ncfg = h->prec == DMRG_FP64 ? CFG_F64_COUNT : CFG_REDUCED_COUNT;
+    const int ncfg = CFG_REDUCED_COUNT;  // the LDS-load FP64 shapes are opt-in, not tuned
     for (int cfg = 0; cfg < ncfg; ++cfg) {
       // the split kernel's 256x128 shape spills registers: not a candidate
       if (h->prec == DMRG_SPLIT_BF16X3 && cfg == CFG_F64_256x128) continue;
@@ -955,5 +998,28 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
   }
   old.release();
   free_graph(h);
-  return DMRG_OK;
+  if (which != 0) return DMRG_OK;
+  // FP64: the per-phase launches or the single persistent launch, whichever
+  // runs the rebuilt program faster (the two give identical results)
+  if ((st = h->pers.build(h->fwdp[0])) != DMRG_OK) return st;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return fail(DMRG_EHIP, "heff_autotune: hipEventCreate failed");
+  }
+  float best[2] = {0.f, 0.f};
+  for (int mode = 0; mode < 2 && st == DMRG_OK; ++mode) {
+    h->persistent = mode;
+    st = heff_apply_eager(h, psi, y);  // warm-up
+    if (st == DMRG_OK && hipEventRecord(t0, s) != hipSuccess) st = fail(DMRG_EHIP, "event");
+    for (int r = 0; r < reps && st == DMRG_OK; ++r) st = heff_apply_eager(h, psi, y);
+    if (st == DMRG_OK && hipEventRecord(t1, s) != hipSuccess) st = fail(DMRG_EHIP, "event");
+    if (st == DMRG_OK && hipEventSynchronize(t1) != hipSuccess) st = fail(DMRG_EHIP, "event sync");
+    if (st == DMRG_OK && hipEventElapsedTime(&best[mode], t0, t1) != hipSuccess) st = fail(DMRG_EHIP, "elapsed");
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st == DMRG_OK) st = h->pers.check(s);
+  h->persistent = st == DMRG_OK && best[1] < best[0] ? 1 : 0;
+  return st;
 }

@@ -129,6 +129,15 @@ class Heff:
     def set_precision(self, prec):
         check(lib().dmrg_heff_set_precision(self.h, int(prec)))
 
+    def set_persistent(self, enable=True):
+        """FP64 matvec as one persistent launch (bit-identical results)."""
+        check(lib().dmrg_heff_set_persistent(self.h, 1 if enable else 0))
+
+    def check(self):
+        """Synchronises; raises if a persistent launch gave up a wait."""
+        self.ctx.sync_stream()
+        check(lib().dmrg_heff_check(self.h))
+
     def use_graph(self, enable=True):
         check(lib().dmrg_heff_use_graph(self.h, 1 if enable else 0))
 

@@ -8,6 +8,7 @@
   the same round-robin pair order the kernel uses.
 """
 import numpy as np
+import pytest
 import torch
 
 
@@ -90,3 +91,86 @@ def test_jacobi_rule_converges_on_decaying_spectrum():
     assert sweeps is not None and sweeps <= 40, sweeps
     ref = np.linalg.svd(A, compute_uv=False)
     assert np.abs(sig - ref).max() <= 1e-13 * ref[0]
+
+
+def _simulate_persistent(ntask, grid, seed, late_start=True):
+    """Discrete-event model of the persistent matvec's scheduling protocol
+    (persist.hip): per-(phase, range) queues taken in phase order, own range
+    first; a workgroup takes its next task when it starts the current one
+    (the next tile's loads are issued early); completions are published with
+    one add when a workgroup moves to a later phase or leaves; before its
+    first task of phase p a workgroup waits until phase p - 1 is complete.
+    Workgroups start at random times (not all resident at once) and tasks
+    take random times.  Returns (start time, phase) and (finish time, phase)
+    of every task, or raises on a deadlock."""
+    import heapq
+    rng = np.random.default_rng(seed)
+    nph = len(ntask)
+    qlen = []
+    for n in ntask:  # eight contiguous ranges per phase
+        cuts = np.sort(rng.integers(0, n + 1, size=7))
+        b = np.concatenate([[0], cuts, [n]])
+        qlen.append(np.diff(b).tolist())
+    head = [[0] * 8 for _ in range(nph)]
+    done = [0] * nph
+
+    def dequeue(g, frm):
+        xq = g % 8
+        for p in range(frm, nph):
+            for i in range(8):
+                q = (xq + i) % 8
+                if head[p][q] < qlen[p][q]:
+                    head[p][q] += 1
+                    return p
+        return None
+
+    finish, starts = [], []
+    state = {g: dict(ph=0, mine=0, run=None, nxt="fetch") for g in range(grid)}
+    events = [(rng.uniform(0, 5.0) if late_start else 0.0, g) for g in range(grid)]
+    heapq.heapify(events)
+    steps = 0
+    while events:
+        now, g = heapq.heappop(events)
+        steps += 1
+        if steps > 10 ** 6 or now > 1e5:
+            raise RuntimeError("deadlock")
+        st = state[g]
+        if st["run"] is not None:  # the running task finished
+            finish.append((now, st["run"]))
+            st["mine"] += 1
+            st["run"] = None
+        if st["nxt"] == "fetch":
+            st["nxt"] = dequeue(g, st["ph"])
+        p = st["nxt"]
+        if p is None:  # leave: publish
+            done[st["ph"]] += st["mine"]
+            st["mine"] = 0
+            continue
+        if p != st["ph"]:  # publish before waiting for the earlier phase
+            done[st["ph"]] += st["mine"]
+            st["mine"] = 0
+            st["ph"] = p
+        if p > 0 and done[p - 1] < ntask[p - 1]:
+            heapq.heappush(events, (now + 0.05, g))  # spin
+            continue
+        st["run"] = p
+        starts.append((now, p))
+        st["nxt"] = dequeue(g, st["ph"])  # fetched ahead, held while this one runs
+        heapq.heappush(events, (now + rng.exponential(1.0), g))
+    assert done == list(ntask)
+    return starts, finish
+
+
+@pytest.mark.parametrize("grid", [8, 9, 24, 96])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_persistent_protocol_drains_in_phase_order(grid, seed):
+    ntask = [37, 5, 120, 1, 64, 9]
+    starts, finish = _simulate_persistent(ntask, grid, seed)
+    assert len(finish) == sum(ntask)
+    # no task of phase p starts before every task of phase p - 1 finished
+    last = {}
+    for t, p in finish:
+        last[p] = max(last.get(p, 0.0), t)
+    for t, p in starts:
+        if p > 0:
+            assert t >= last[p - 1]
