@@ -72,3 +72,19 @@ def fci_energy(h, V, n_a, n_b, dense: bool = False):
         return float(np.linalg.eigvalsh(H.toarray())[0])
     w = spla.eigsh(H, k=1, which="SA", tol=1e-14, maxiter=100000)[0]
     return float(w[0])
+
+
+def fci_rdm1(h, V, n_a, n_b):
+    """Ground state of the (n_a, n_b) sector by dense diagonalisation and its
+    spin-summed one-particle density matrix gamma_pq = <Psi|E_pq|Psi>.
+    Returns (E0, gamma, gap to the next eigenvalue); gamma is defined only
+    for a non-degenerate ground state (the gap says whether it is)."""
+    n = h.shape[0]
+    fs = FockSpace(n)
+    H, idx = fci_hamiltonian(h, V, n_a, n_b, fs)
+    w, U = np.linalg.eigh(H.toarray())
+    c = U[:, 0]
+    E = excitation_ops(fs, idx)
+    gamma = np.array([[c @ (E[p][q] @ c) for q in range(n)] for p in range(n)])
+    gap = float(w[1] - w[0]) if len(w) > 1 else np.inf
+    return float(w[0]), gamma, gap

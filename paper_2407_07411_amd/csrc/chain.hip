@@ -22,11 +22,15 @@
 //   z (x) E_z for two-operator z on the left (E_z a sum of right products),
 //   C3_L[y] (x) y for one-operator y on the right,
 // handed to the grouped-GEMM plan; Davidson, SVD truncation and the
-// renormalisation O <- U^T O U close the step.  The operator algebra runs on
-// the host (blocks of a few hundred states); H_eff, Davidson and the SVD run
-// in the library's kernels.
+// renormalisation O <- U^T O U close the step.  The growth (block operators
+// times 4x4 site operators, placed into the enlarged blocks) runs on the
+// host; the renormalisation of every operator, H_eff, Davidson and the SVD
+// run in the library's kernels when the chain has a context (the
+// renormalisation as two grouped-GEMM phases, T = O U_in and U_out^T T, over
+// all operators of the block at once).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -440,6 +444,125 @@ Block renorm_block(const Block& E, const Basis& to, const std::vector<int>& map_
   return B;
 }
 
+// The same renormalisation on the device: for every (operator, input sector)
+// pair the two products T = O U_in and O' = U_out^T T run as the two phases
+// of one grouped-GEMM program (the matvec's kernels), with the operator
+// blocks, the isometries and the results in device buffers.
+dmrg_status renorm_block_dev(dmrg_ctx_t ctx, const Block& E, const Basis& to, const std::vector<int>& map_to,
+                             const std::vector<std::vector<double>>& U, Block* out) {
+  std::vector<const Op*> ops{&E.H};
+  for (auto& kv : E.ops) ops.push_back(&kv.second);
+  for (auto& kv : E.comp) ops.push_back(&kv.second);
+  std::vector<double> opool, upool;
+  std::vector<int64_t> uoff(E.b.qn.size(), -1);
+  for (size_t sec = 0; sec < E.b.qn.size(); ++sec)
+    if (map_to[sec] >= 0) {
+      uoff[sec] = (int64_t)upool.size();
+      upool.insert(upool.end(), U[sec].begin(), U[sec].end());
+    }
+  struct Job {
+    int op, in, out;
+    int64_t ooff, toff, roff;
+  };
+  std::vector<Job> jobs;
+  int64_t work = 0, res = 0;
+  for (size_t o = 0; o < ops.size(); ++o) {
+    const Op& O = *ops[o];
+    for (size_t in = 0; in < E.b.qn.size(); ++in) {
+      if (O.blk[in].empty() || map_to[in] < 0) continue;
+      const int outs = E.b.out_of((int)in, O.dq);
+      if (outs < 0 || map_to[outs] < 0) continue;
+      const int dout = E.b.dim[outs], kin = to.dim[map_to[in]], kout = to.dim[map_to[outs]];
+      jobs.push_back(Job{(int)o, (int)in, outs, (int64_t)opool.size(), work, res});
+      opool.insert(opool.end(), O.blk[in].begin(), O.blk[in].end());
+      work += (int64_t)dout * kin;
+      res += (int64_t)kout * kin;
+    }
+  }
+  Block R;
+  R.b = to;
+  R.orbs = E.orbs;
+  R.H = zero_op(to, E.H.dq);
+  for (auto& kv : E.ops) R.ops[kv.first] = zero_op(to, kv.second.dq);
+  for (auto& kv : E.comp) R.comp[kv.first] = zero_op(to, kv.second.dq);
+  std::vector<Op*> outs{&R.H};
+  for (auto& kv : R.ops) outs.push_back(&kv.second);
+  for (auto& kv : R.comp) outs.push_back(&kv.second);
+  if (jobs.empty()) {
+    *out = std::move(R);
+    return DMRG_OK;
+  }
+  ProgramBuilder pb;
+  for (const Job& j : jobs) {  // T = O U_in (dout x kin), K = din
+    const int din = E.b.dim[j.in], dout = E.b.dim[j.out], kin = to.dim[map_to[j.in]];
+    const int32_t pr = pb.add_prob(BUF_WORK, j.toff, dout, kin, kin, false);
+    pb.add_seg(pr, make_seg(BUF_LPOOL, j.ooff, din, false, BUF_RPOOL, uoff[j.in], kin, false, din, 1.0));
+  }
+  pb.phase_id = 0;
+  pb.close_phase();
+  for (const Job& j : jobs) {  // O' = U_out^T T (kout x kin), K = dout
+    const int dout = E.b.dim[j.out], kin = to.dim[map_to[j.in]], kout = to.dim[map_to[j.out]];
+    const int32_t pr = pb.add_prob(BUF_Y, j.roff, kout, kin, kin, false);
+    pb.add_seg(pr, make_seg(BUF_RPOOL, uoff[j.out], kout, true, BUF_WORK, j.toff, kin, false, dout, 1.0));
+  }
+  pb.phase_id = 1;
+  pb.close_phase();
+  Program& P = pb.prog;
+  int64_t len[BUF_COUNT] = {0, res, (int64_t)opool.size(), (int64_t)upool.size(), work, 0, 0, 0, P.part_elems};
+  dmrg_status st = P.validate(len);
+  if (st != DMRG_OK) return st;
+  double *dO = nullptr, *dU = nullptr, *dT = nullptr, *dR = nullptr, *dP = nullptr;
+  auto cleanup = [&]() {
+    P.release();
+    for (double* q : {dO, dU, dT, dR, dP})
+      if (q) (void)hipFree(q);
+  };
+  if (hipMalloc(&dO, opool.size() * 8) != hipSuccess || hipMalloc(&dU, upool.size() * 8) != hipSuccess ||
+      hipMalloc(&dT, work * 8) != hipSuccess || hipMalloc(&dR, res * 8) != hipSuccess ||
+      hipMalloc(&dP, std::max<int64_t>(P.part_elems, 1) * 8) != hipSuccess) {
+    cleanup();
+    return fail(DMRG_ENOMEM, "chain: renormalisation buffers");
+  }
+  hipStream_t s = ctx->stream;
+  if ((st = P.upload()) == DMRG_OK) {
+    Bases b{};
+    b.p[BUF_Y] = dR;
+    b.p[BUF_LPOOL] = dO;
+    b.p[BUF_RPOOL] = dU;
+    b.p[BUF_WORK] = dT;
+    b.p[BUF_PART] = dP;
+    for (int k = 0; k < BUF_COUNT; ++k) b.len[k] = len[k];
+    std::vector<double> host(res);
+    if (hipMemcpyAsync(dO, opool.data(), opool.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(dU, upool.data(), upool.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+      st = fail(DMRG_EHIP, "chain: renormalisation copy");
+    if (st == DMRG_OK) st = P.run(b, s, DMRG_FP64);
+    if (st == DMRG_OK && (hipMemcpyAsync(host.data(), dR, res * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                          hipStreamSynchronize(s) != hipSuccess))
+      st = fail(DMRG_EHIP, "chain: renormalisation copy");
+    if (st == DMRG_OK) {
+      for (const Job& j : jobs) {
+        const int kin = to.dim[map_to[j.in]], kout = to.dim[map_to[j.out]];
+        outs[j.op]->blk[map_to[j.in]].assign(host.begin() + j.roff, host.begin() + j.roff + (int64_t)kout * kin);
+      }
+      *out = std::move(R);
+    }
+  }
+  cleanup();
+  return st;
+}
+
+// Host (DMRG_CHAIN_HOST_RENORM=1) or device renormalisation.
+dmrg_status renorm_any(dmrg_ctx_t ctx, const Block& E, const Basis& to, const std::vector<int>& map_to,
+                       const std::vector<std::vector<double>>& U, Block* out) {
+  const char* e = std::getenv("DMRG_CHAIN_HOST_RENORM");
+  if (!ctx || (e && std::atoi(e) != 0)) {
+    *out = renorm_block(E, to, map_to, U);
+    return DMRG_OK;
+  }
+  return renorm_block_dev(ctx, E, to, map_to, U, out);
+}
+
 std::vector<double> identity(int d) {
   std::vector<double> I((size_t)d * d, 0.0);
   for (int i = 0; i < d; ++i) I[(size_t)i * d + i] = 1.0;
@@ -636,11 +759,11 @@ dmrg_status dmrg_chain_create(dmrg_ctx_t ctx, int32_t L, const double* h, const 
         to.dim.push_back(k[map[i]]);
         U[i] = random_isometry(c->rng, E.b.dim[i], k[map[i]]);
       }
-      c->right[j] = renorm_block(E, to, map2, U);
+      if (dmrg_status st = renorm_any(ctx, E, to, map2, U, &c->right[j]); st != DMRG_OK) return st;
     } else {
       for (size_t i = 0; i < E.b.qn.size(); ++i)
         if (map[i] >= 0) U[i] = identity(E.b.dim[i]);
-      c->right[j] = renorm_block(E, kept, map, U);
+      if (dmrg_status st = renorm_any(ctx, E, kept, map, U, &c->right[j]); st != DMRG_OK) return st;
     }
   }
   *out = c.release();
@@ -661,7 +784,7 @@ dmrg_status dmrg_chain_grow_left(dmrg_chain_t c, int32_t l) {
     std::vector<std::vector<double>> U(E.b.qn.size());
     for (size_t i = 0; i < E.b.qn.size(); ++i)
       if (map[i] >= 0) U[i] = identity(E.b.dim[i]);
-    c->left[j + 1] = renorm_block(E, kept, map, U);
+    if (dmrg_status st = renorm_any(c->ctx, E, kept, map, U, &c->left[j + 1]); st != DMRG_OK) return st;
   }
   return DMRG_OK;
 }
@@ -837,9 +960,9 @@ dmrg_status dmrg_chain_step(dmrg_chain_t c, int32_t l, int32_t dir, const dmrg_d
             toR.dim.push_back((int)(WR[r].size() / Re.b.dim[r]));
           }
         if (dir == 1)
-          c->left[l + 1] = renorm_block(Le, toL, mapL, UL);
+          st = renorm_any(c->ctx, Le, toL, mapL, UL, &c->left[l + 1]);
         else
-          c->right[l + 1] = renorm_block(Re, toR, mapR, WR);
+          st = renorm_any(c->ctx, Re, toR, mapR, WR, &c->right[l + 1]);
       }
     }
   }
