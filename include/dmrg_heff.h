@@ -129,6 +129,38 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
                              const double* left_pool, int64_t left_pool_len,
                              const double* right_pool, int64_t right_pool_len,
                              dmrg_prec prec, dmrg_heff_t* out);
+/* Out-of-core form of dmrg_heff_create for operators larger than device
+ * memory, the regime where the paper finds host-device traffic dominating
+ * (Performance assessment section, beyond D of about 8000-10000) and hides
+ * it with asynchronous transfers.  left_pool_host / right_pool_host: the
+ * same pools in page-locked host memory (hipHostMalloc; pageable or device
+ * memory is refused with DMRG_EINVAL), borrowed and read by later applies;
+ * unlike device pools their contents must not change after creation (part
+ * of them is copied to the device once).  device_bytes bounds the device memory that
+ * holds operator blocks (the workspace of dmrg_heff_create comes on top):
+ * when every distinct block fits, all are copied once at creation;
+ * otherwise two staging slots (DMRG_HEFF_STREAM_SLOT_KB, else a quarter of
+ * the budget, at most 4 GiB, at least the largest pair's blocks) are set
+ * aside, the items whose blocks fit the rest are copied once, and every
+ * apply copies the remaining blocks slot by slot on a copy stream while the
+ * compute stream runs the resident items and the slot filled before.
+ * Results match dmrg_heff_create's to rounding (the waves, hence the
+ * summation order into y, differ).  apply, diag and Davidson work as for
+ * device pools (Davidson without stage graphs); use_graph, the persistent
+ * launch, autotune, apply_profiled and the adjoint return DMRG_ENOTSUP.
+ * Errors: as dmrg_heff_create; DMRG_ENOMEM when two slots of the largest
+ * pair exceed device_bytes.  DMRG_HEFF_STREAM_RESIDENT_KB caps the resident
+ * copy (0: stream every pair).  Synchronises the context stream. */
+dmrg_status dmrg_heff_create_streamed(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
+                                      const int32_t Q[2], int64_t n_terms, const dmrg_term* terms,
+                                      const double* left_pool_host, int64_t left_pool_len,
+                                      const double* right_pool_host, int64_t right_pool_len,
+                                      dmrg_prec prec, int64_t device_bytes, dmrg_heff_t* out);
+/* Host, synchronous.  Bytes of operator blocks held on the device for the
+ * whole plan, bytes copied from host memory per apply, and the number of
+ * resident and streamed waves (all zero for a plan over device pools). */
+dmrg_status dmrg_heff_stream_info(dmrg_heff_t h, int64_t* resident_bytes, int64_t* streamed_bytes,
+                                  int32_t* resident_waves, int32_t* streamed_waves);
 void dmrg_heff_destroy(dmrg_heff_t h);
 dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec);
 /* Host, synchronous.  alg_flops: FP64-equivalent FLOPs of one matvec, every

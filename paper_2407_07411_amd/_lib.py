@@ -51,6 +51,11 @@ SIGNATURES = {
                                 POINTER(c_int64)]),
     "dmrg_heff_create": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_int64, POINTER(Term),
                                  c_void_p, c_int64, c_void_p, c_int64, c_int, POINTER(c_void_p)]),
+    "dmrg_heff_create_streamed": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_int64, POINTER(Term),
+                                          c_void_p, c_int64, c_void_p, c_int64, c_int, c_int64,
+                                          POINTER(c_void_p)]),
+    "dmrg_heff_stream_info": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
+                                      POINTER(c_int32)]),
     "dmrg_heff_destroy": (None, [c_void_p]),
     "dmrg_heff_set_precision": (c_int, [c_void_p, c_int]),
     "dmrg_heff_set_persistent": (c_int, [c_void_p, c_int32]),

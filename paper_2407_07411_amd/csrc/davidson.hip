@@ -589,6 +589,9 @@ dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts, const
   if (!d) return fail(DMRG_ENOMEM, "davidson_create: out of host memory");
   d->h = h;
   d->o = o;
+  // out-of-core operators: the matvec's copies and cross-stream waits stay
+  // eager, so the stages run without graphs
+  if (h->strm.on) d->o.use_graph = 0;
   const int64_t n = h->size;
   d->n = n;
   const int kmax = o.max_subspace, keep = o.restart_keep;

@@ -52,11 +52,12 @@ dmrg_status Program::upload() {
   return DMRG_OK;
 }
 
-dmrg_status Program::validate(const int64_t* len) const {
+dmrg_status Program::validate_probs(const int64_t* len, size_t p0, size_t p1) const {
   auto in = [&](uint8_t buf, int64_t lo, int64_t hi) {  // [lo, hi] inclusive
     return buf < BUF_COUNT && lo >= 0 && hi < len[buf];
   };
-  for (size_t pi = 0; pi < probs.size(); ++pi) {
+  if (p0 > p1 || p1 > probs.size()) return fail(DMRG_EQN, "plan: problem range outside the table");
+  for (size_t pi = p0; pi < p1; ++pi) {
     const Prob& p = probs[pi];
     if (p.M < 1 || p.N < 1 || p.ldc < p.N || p.seg0 < 0 || p.nseg < 0 ||
         (size_t)p.seg0 + p.nseg > segs.size())
@@ -76,6 +77,14 @@ dmrg_status Program::validate(const int64_t* len) const {
         return fail(DMRG_EQN, "plan: operand of problem " + std::to_string(pi) + " out of bounds");
     }
   }
+  return DMRG_OK;
+}
+
+dmrg_status Program::validate(const int64_t* len) const {
+  auto in = [&](uint8_t buf, int64_t lo, int64_t hi) {  // [lo, hi] inclusive
+    return buf < BUF_COUNT && lo >= 0 && hi < len[buf];
+  };
+  if (dmrg_status st = validate_probs(len, 0, probs.size()); st != DMRG_OK) return st;
   for (size_t ri = 0; ri < reds.size(); ++ri) {
     const RedBlock& r = reds[ri];
     if (r.M < 1 || r.N < 1 || r.ldc < r.N || r.part0 < 0 || r.nparts < 1 ||
@@ -142,8 +151,13 @@ dmrg_status Program::prepare_concurrent() {
 }
 
 dmrg_status Program::run(const Bases& b, hipStream_t s, int precision) const {
-  if (concurrent && s != nullptr) return run_concurrent(b, s, precision);
-  for (const Launch& l : launches) {
+  return run_range(b, s, precision, 0, launches.size());
+}
+
+dmrg_status Program::run_range(const Bases& b, hipStream_t s, int precision, size_t l0, size_t l1) const {
+  if (concurrent && s != nullptr) return run_concurrent(b, s, precision, l0, l1);
+  for (size_t i = l0; i < l1; ++i) {
+    const Launch& l = launches[i];
     Launch x = l;
     x.split = precision;
     dmrg_status st = l.cfg == CFG_REDUCE ? launch_reduce(x, b, d_reds, d_red_parts, s)
@@ -169,14 +183,15 @@ dmrg_status launch_one(const Launch& l, const Bases& b, const Program& P, hipStr
 // the partial sums are not touched there), and the phase after it waits for
 // the reduction.  Every side stream is joined into s before returning, so the
 // caller sees one ordered operation (and a graph capture on s closes).
-dmrg_status Program::run_concurrent(const Bases& b, hipStream_t s, int precision) const {
+dmrg_status Program::run_concurrent(const Bases& b, hipStream_t s, int precision, size_t l0,
+                                    size_t l1) const {
   size_t ev = 0;
   hipEvent_t pending = nullptr;  // reduction still running on side[1]
   int pending_phase = -1;
-  for (size_t i = 0; i < launches.size();) {
+  for (size_t i = l0; i < l1;) {
     const int ph = launches[i].phase;
     size_t j = i;
-    while (j < launches.size() && launches[j].phase == ph) ++j;
+    while (j < l1 && launches[j].phase == ph) ++j;
     if (pending && ph - pending_phase >= 2) {
       DMRG_HIP(hipStreamWaitEvent(s, pending, 0));
       pending = nullptr;
@@ -207,7 +222,7 @@ dmrg_status Program::run_concurrent(const Bases& b, hipStream_t s, int precision
       if (st != DMRG_OK) return st;
     }
     if (red) {
-      const bool next_intermediate = j < launches.size() && launches[j].ptype == 0;
+      const bool next_intermediate = j < l1 && launches[j].ptype == 0;
       if (next_intermediate) {
         if (pending) {  // at most one reduction in flight
           DMRG_HIP(hipStreamWaitEvent(s, pending, 0));

@@ -133,6 +133,9 @@ struct Program {
   std::vector<RedBlock> reds;
   std::vector<int64_t> red_parts;  // offsets of partials in BUF_PART
   int64_t part_elems = 0;          // BUF_PART doubles needed
+  // First problem and first launch of each workspace wave (one entry per
+  // wave plus the end), in execution order.
+  std::vector<int64_t> wave_prob0, wave_launch0;
   Prob* d_probs = nullptr;
   Seg* d_segs = nullptr;
   Tile* d_tiles = nullptr;
@@ -143,7 +146,11 @@ struct Program {
   // Host-side bounds proof of every access the kernels will make, given the
   // length (in doubles) of each buffer id.  Run before the first launch.
   dmrg_status validate(const int64_t* buf_len) const;
+  // The problem part of that proof for problems [p0, p1) only.
+  dmrg_status validate_probs(const int64_t* buf_len, size_t p0, size_t p1) const;
   dmrg_status run(const Bases& b, hipStream_t s, int precision) const;
+  // Launches [l0, l1) only (a whole number of phases), in the same form.
+  dmrg_status run_range(const Bases& b, hipStream_t s, int precision, size_t l0, size_t l1) const;
   // Two-stream execution (set for the forward program): within a phase the
   // smaller tile shapes run beside the largest one, and a phase's K-split
   // reduction runs beside the next phase when that one writes intermediates
@@ -151,7 +158,7 @@ struct Program {
   bool concurrent = false;
   mutable hipStream_t side[2] = {nullptr, nullptr};
   mutable std::vector<hipEvent_t> events;
-  dmrg_status run_concurrent(const Bases& b, hipStream_t s, int precision) const;
+  dmrg_status run_concurrent(const Bases& b, hipStream_t s, int precision, size_t l0, size_t l1) const;
   dmrg_status prepare_concurrent();
 };
 

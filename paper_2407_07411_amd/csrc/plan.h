@@ -86,7 +86,50 @@ struct Persist {
   dmrg_status check(hipStream_t s) const;  // synchronises; reports a give-up
 };
 
+// Out-of-core form: the operator pools stay in the caller's pinned host
+// memory.  The items are grouped in waves (ranges of the item list); a
+// resident wave reads a device copy of its blocks made once at creation, a
+// streamed wave reads one of two staging slots that a copy stream fills
+// while earlier waves compute (stream.hip).
+struct StreamRun {   // one host-to-device copy
+  int64_t src, dst, n;  // doubles: offset in the host pool, in the wave's buffer, length
+  uint8_t side;         // 0: left pool, 1: right pool
+};
+struct StreamWave {
+  size_t item0, item1;  // item range
+  int32_t slot;         // -1: resident copy, else the staging slot
+  int64_t run0, nrun;   // copies of a streamed wave
+  int64_t len;          // doubles of the buffer the wave reads
+};
+struct StreamPlan {
+  bool on = false;
+  std::vector<StreamWave> waves;  // execution order
+  std::vector<StreamRun> runs;
+  std::vector<int64_t> aoff, boff;  // per item: block offsets in its wave's buffer
+  double* cache = nullptr;          // resident blocks, left runs then right runs
+  int64_t cache_elems = 0;
+  double* slot[2] = {nullptr, nullptr};
+  int64_t slot_elems = 0;
+  double* diag = nullptr;           // diagonals of the square dq = 0 blocks, compact
+  int64_t streamed_elems = 0;       // doubles copied per matvec
+  int32_t n_streamed = 0;           // streamed waves
+  hipStream_t copy = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+  void release();
+};
+
 dmrg_status heff_apply_eager(struct ::dmrg_heff_s* h, const double* psi, double* y);
+// Workspace doubles of one item's intermediate (0 for one-sided items) and
+// its association order (left operator first when cheaper or equal).
+int64_t item_need(const struct ::dmrg_heff_s* h, const Item& it, bool* left_first);
+// Groups the items into resident and streamed waves for a device budget of
+// `device_bytes`, copies the resident blocks and allocates the slots.
+dmrg_status build_stream_plan(struct ::dmrg_heff_s* h, int64_t device_bytes);
+// Runs the forward program of the current precision wave by wave.
+dmrg_status stream_apply(struct ::dmrg_heff_s* h, const Bases& b);
+// Diagonal tables of the out-of-core form: square blocks' diagonals gathered
+// from the host pools into one compact device array.
+dmrg_status stream_diag_tables(struct ::dmrg_heff_s* h, std::vector<DiagItem>& items);
 Seg make_seg(uint8_t xbuf, int64_t xoff, int ldx, bool xt, uint8_t zbuf, int64_t zoff, int ldz,
              bool zt, int K, double alpha);
 int choose_cfg(int M, int N, bool split);
@@ -132,6 +175,8 @@ struct dmrg_heff_s {
   dmrg::DiagItem* d_ditems = nullptr;
   int n_dblocks = 0;
   int64_t max_block_elems = 0;
+  // out-of-core operators (lpool / rpool are then pinned host memory)
+  dmrg::StreamPlan strm;
   // persistent single-launch form of the FP64 forward program
   dmrg::Persist pers;
   int persistent = 0;

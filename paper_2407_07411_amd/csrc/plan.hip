@@ -68,6 +68,21 @@ void item_costs(const dmrg_heff_s* h, const Item& it, double* lf, double* rf) {
   *rf = 2.0 * dli * dri * dro + 2.0 * dlo * dli * dro;
 }
 
+}  // namespace
+
+int64_t dmrg::item_need(const dmrg_heff_s* h, const Item& it, bool* left_first) {
+  *left_first = true;
+  if (it.kind != 0) return 0;
+  double lf, rf;
+  item_costs(h, it, &lf, &rf);
+  *left_first = lf <= rf;
+  const BlockInfo& bi = h->blocks[it.in];
+  const BlockInfo& bo = h->blocks[it.out];
+  return *left_first ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
+}
+
+namespace {
+
 dmrg_status build_items(dmrg_heff_s* h, int64_t n_terms, const dmrg_term* terms) {
   const int nL = (int)h->Ld.size(), nR = (int)h->Rd.size();
   auto findL = [&](int32_t n, int32_t s) {
@@ -234,32 +249,47 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
   for (size_t i = 0; i < ni; ++i) {
     const Item& it = h->items[i];
     reached[it.out] = 1;
-    if (it.kind != 0) continue;
-    double lf, rf;
-    item_costs(h, it, &lf, &rf);
-    lf_first[i] = lf <= rf ? 1 : 0;
-    const BlockInfo& bi = h->blocks[it.in];
-    const BlockInfo& bo = h->blocks[it.out];
-    need[i] = lf_first[i] ? (int64_t)bo.dl * bi.dr : (int64_t)bi.dl * bo.dr;
+    bool lf = true;
+    need[i] = item_need(h, it, &lf);
+    lf_first[i] = lf ? 1 : 0;
     max_need = std::max(max_need, need[i]);
   }
   const int64_t budget = std::max(h->work_budget, max_need);
+  // waves: the out-of-core plan's (its order, each within the budget), or
+  // consecutive item ranges that fill the workspace
   std::vector<std::pair<size_t, size_t>> waves;
-  size_t w0 = 0;
-  int64_t used = 0, peak = 0;
-  for (size_t i = 0; i < ni; ++i) {
-    if (used + need[i] > budget && i > w0) {
-      waves.push_back({w0, i});
-      w0 = i;
-      used = 0;
+  if (h->strm.on) {
+    for (const StreamWave& w : h->strm.waves) waves.push_back({w.item0, w.item1});
+  } else {
+    size_t w0 = 0;
+    int64_t used = 0;
+    for (size_t i = 0; i < ni; ++i) {
+      if (used + need[i] > budget && i > w0) {
+        waves.push_back({w0, i});
+        w0 = i;
+        used = 0;
+      }
+      used += need[i];
     }
-    woff[i] = used;
-    used += need[i];
+    waves.push_back({w0, ni});
+  }
+  int64_t peak = 0;
+  for (const auto& w : waves) {
+    int64_t used = 0;
+    for (size_t i = w.first; i < w.second; ++i) {
+      woff[i] = used;
+      used += need[i];
+    }
+    if (used > budget && w.second - w.first > 1) return fail(DMRG_EQN, "plan: wave exceeds the workspace");
     peak = std::max(peak, used);
   }
-  waves.push_back({w0, ni});
   h->work_elems = std::max<int64_t>(peak, 1);
+  // operator block offsets: the pools', or those in each wave's buffer
+  auto A = [&](size_t i) { return h->strm.on ? h->strm.aoff[i] : h->items[i].aoff; };
+  auto B = [&](size_t i) { return h->strm.on ? h->strm.boff[i] : h->items[i].boff; };
   for (size_t w = 0; w < waves.size(); ++w) {
+    pb.prog.wave_prob0.push_back((int64_t)pb.prog.probs.size());
+    pb.prog.wave_launch0.push_back((int64_t)pb.prog.launches.size());
     // phase 1
     for (size_t i = waves[w].first; i < waves[w].second; ++i) {
       const Item& it = h->items[i];
@@ -271,12 +301,12 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
       if (lf_first[i]) {
         int32_t p = pb.add_prob(BUF_WORK, woff[i], bo.dl, bi.dr, bi.dr, false);
         opA_as_x(it, &xt, &ldx);
-        pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
+        pb.add_seg(p, make_seg(BUF_LPOOL, A(i), ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
                                it.alpha));
       } else {
         int32_t p = pb.add_prob(BUF_WORK, woff[i], bi.dl, bo.dr, bo.dr, false);
         opBt_as_z(it, &zt, &ldz);
-        pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt, bi.dr,
+        pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, B(i), ldz, zt, bi.dr,
                                it.alpha));
       }
     }
@@ -299,19 +329,19 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
         int ldx, ldz;
         if (it.kind == 1) {
           opA_as_x(it, &xt, &ldx);
-          pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
+          pb.add_seg(p, make_seg(BUF_LPOOL, A(i), ldx, xt, BUF_PSI, bi.off, bi.dr, false, bi.dl,
                                  it.alpha));
         } else if (it.kind == 2) {
           opBt_as_z(it, &zt, &ldz);
-          pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, it.boff, ldz, zt, bi.dr,
+          pb.add_seg(p, make_seg(BUF_PSI, bi.off, bi.dr, false, BUF_RPOOL, B(i), ldz, zt, bi.dr,
                                  it.alpha));
         } else if (lf_first[i]) {
           opBt_as_z(it, &zt, &ldz);
-          pb.add_seg(p, make_seg(BUF_WORK, woff[i], bi.dr, false, BUF_RPOOL, it.boff, ldz, zt,
+          pb.add_seg(p, make_seg(BUF_WORK, woff[i], bi.dr, false, BUF_RPOOL, B(i), ldz, zt,
                                  bi.dr, 1.0));
         } else {
           opA_as_x(it, &xt, &ldx);
-          pb.add_seg(p, make_seg(BUF_LPOOL, it.aoff, ldx, xt, BUF_WORK, woff[i], bo.dr, false,
+          pb.add_seg(p, make_seg(BUF_LPOOL, A(i), ldx, xt, BUF_WORK, woff[i], bo.dr, false,
                                  bi.dl, 1.0));
         }
       }
@@ -319,6 +349,8 @@ dmrg_status build_forward(dmrg_heff_s* h, int cfg_override, int which) {
     pb.phase_id = 1;
     pb.close_phase();
   }
+  pb.prog.wave_prob0.push_back((int64_t)pb.prog.probs.size());
+  pb.prog.wave_launch0.push_back((int64_t)pb.prog.launches.size());
   h->fwdp[which] = std::move(pb.prog);
   return DMRG_OK;
 }
@@ -496,6 +528,10 @@ dmrg_status build_diag(dmrg_heff_s* h) {
     h->max_block_elems = std::max<int64_t>(h->max_block_elems, (int64_t)B.dl * B.dr);
   }
   h->n_dblocks = nb;
+  if (h->strm.on) {
+    dmrg_status st = stream_diag_tables(h, di);
+    if (st != DMRG_OK) return st;
+  }
   if (hipMalloc(&h->d_dblocks, std::max<size_t>(1, db.size()) * sizeof(DiagBlock)) != hipSuccess ||
       hipMalloc(&h->d_ditems, std::max<size_t>(1, di.size()) * sizeof(DiagItem)) != hipSuccess)
     return fail(DMRG_ENOMEM, "hipMalloc of diagonal tables failed");
@@ -559,17 +595,21 @@ dmrg_status heff_apply_eager(dmrg_heff_s* h, const double* psi, double* y) {
   const Bases b = fwd_bases(h, psi, y);
   dmrg_status st = fwd_prologue(h, psi, b);
   if (st != DMRG_OK) return st;
+  if (h->strm.on) return stream_apply(h, b);
   if (h->persistent && h->prec == DMRG_FP64) return h->pers.run(b, h->fwdp[0], h->ctx->stream, h->spin_limit);
   return h->fwd().run(b, h->ctx->stream, h->prec);
 }
 }  // namespace dmrg
 
-extern "C" {
+namespace {
 
-dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
-                             int64_t n_terms, const dmrg_term* terms, const double* left_pool,
-                             int64_t left_pool_len, const double* right_pool,
-                             int64_t right_pool_len, dmrg_prec prec, dmrg_heff_t* out) {
+// Plan creation; device_bytes < 0: the pools are device memory, else they
+// are pinned host memory and device_bytes bounds the device copies of their
+// blocks (out-of-core form).
+dmrg_status heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                        int64_t n_terms, const dmrg_term* terms, const double* left_pool,
+                        int64_t left_pool_len, const double* right_pool, int64_t right_pool_len,
+                        dmrg_prec prec, int64_t device_bytes, dmrg_heff_t* out) {
   if (!out) return fail(DMRG_EINVAL, "heff_create: out is NULL");
   *out = nullptr;
   if (!ctx || !L || !R || !Q || n_terms < 0 || (n_terms > 0 && !terms))
@@ -609,64 +649,96 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
   for (const BlockInfo& b : h->blocks)
     if (b.dl > 32767 * 32 || b.dr > 32767 * 32)
       return fail(DMRG_ENOTSUP, "heff_create: sector too large");
+  // every failure from here on frees what the plan holds so far
+  auto bail = [&](dmrg_status e) {
+    dmrg_heff_destroy(h.release());
+    return e;
+  };
   dmrg_status st = build_items(h.get(), n_terms, terms);
-  if (st != DMRG_OK) return st;
+  if (st != DMRG_OK) return bail(st);
   count_work(h.get());
   h->work_budget = workspace_budget_doubles();
+  if (device_bytes >= 0 && (st = build_stream_plan(h.get(), device_bytes)) != DMRG_OK) return bail(st);
   int64_t part_elems = 0;
   for (int which = 0; which < 3; ++which) {
-    if ((st = build_forward(h.get(), cfg_from_env(), which)) != DMRG_OK) return st;
+    if ((st = build_forward(h.get(), cfg_from_env(), which)) != DMRG_OK) return bail(st);
     part_elems = std::max(part_elems, h->fwdp[which].part_elems);
   }
   for (int which = 0; which < 3; ++which) {
+    const Program& P = h->fwdp[which];
     int64_t len[BUF_COUNT] = {h->size, h->size, h->llen, h->rlen, h->work_elems, 0, 0, 0, part_elems};
-    if ((st = h->fwdp[which].validate(len)) != DMRG_OK) return st;
+    if (h->strm.on) {
+      // each wave reads its own operator buffer: prove its problems against
+      // that buffer's length, the rest against the whole program's
+      int64_t longest = 0;
+      for (size_t w = 0; w < h->strm.waves.size(); ++w) {
+        len[BUF_LPOOL] = len[BUF_RPOOL] = h->strm.waves[w].len;
+        longest = std::max(longest, h->strm.waves[w].len);
+        if ((st = P.validate_probs(len, P.wave_prob0[w], P.wave_prob0[w + 1])) != DMRG_OK) return bail(st);
+      }
+      len[BUF_LPOOL] = len[BUF_RPOOL] = longest;
+    }
+    if ((st = P.validate(len)) != DMRG_OK) return bail(st);
   }
   h->split_pack = !unpacked_from_env();
-  if ((st = check_packed_outputs(h->fwdp[1])) != DMRG_OK) return st;
-  for (int which = 0; which < 3 && st == DMRG_OK; ++which) {
-    st = h->fwdp[which].upload();
-    if (st == DMRG_OK && !serial_from_env()) st = h->fwdp[which].prepare_concurrent();
-  }
-  if (st != DMRG_OK) {
-    for (auto& p : h->fwdp) p.release();
-    return st;
+  if ((st = check_packed_outputs(h->fwdp[1])) != DMRG_OK) return bail(st);
+  for (int which = 0; which < 3; ++which) {
+    if ((st = h->fwdp[which].upload()) != DMRG_OK) return bail(st);
+    if (!serial_from_env() && (st = h->fwdp[which].prepare_concurrent()) != DMRG_OK) return bail(st);
   }
   h->part_elems = part_elems;
   if (hipMalloc(&h->part, std::max<int64_t>(part_elems, 1) * sizeof(double)) != hipSuccess) {
     h->part = nullptr;
-    for (auto& p : h->fwdp) p.release();
-    return fail(DMRG_ENOMEM, "heff_create: partial-sum buffer allocation failed");
+    return bail(fail(DMRG_ENOMEM, "heff_create: partial-sum buffer allocation failed"));
   }
   if (hipMalloc(&h->work, h->work_elems * sizeof(double)) != hipSuccess) {
     h->work = nullptr;
-    for (auto& p : h->fwdp) p.release();
-    (void)hipFree(h->part);
-    return fail(DMRG_ENOMEM, "heff_create: workspace allocation failed");
+    return bail(fail(DMRG_ENOMEM, "heff_create: workspace allocation failed"));
   }
   if (hipMalloc(&h->psi_pk, h->size * sizeof(double)) != hipSuccess) {
     h->psi_pk = nullptr;
-    for (auto& p : h->fwdp) p.release();
-    (void)hipFree(h->work);
-    (void)hipFree(h->part);
-    return fail(DMRG_ENOMEM, "heff_create: pre-split vector allocation failed");
+    return bail(fail(DMRG_ENOMEM, "heff_create: pre-split vector allocation failed"));
   }
-  if ((st = build_diag(h.get())) != DMRG_OK) {
-    for (auto& p : h->fwdp) p.release();
-    (void)hipFree(h->psi_pk);
-    (void)hipFree(h->work);
-    (void)hipFree(h->part);
-    return st;
-  }
+  if ((st = build_diag(h.get())) != DMRG_OK) return bail(st);
   if (const char* e = std::getenv("DMRG_HEFF_SPIN_TICKS")) h->spin_limit = std::atoll(e);
-  dmrg_heff_s* hp = h.release();
-  if (const char* e = std::getenv("DMRG_HEFF_PERSIST"); e && std::atoi(e) != 0) {
-    if ((st = dmrg_heff_set_persistent(hp, 1)) != DMRG_OK) {
-      dmrg_heff_destroy(hp);
-      return st;
-    }
+  if (const char* e = std::getenv("DMRG_HEFF_PERSIST"); e && std::atoi(e) != 0 && !h->strm.on) {
+    if ((st = dmrg_heff_set_persistent(h.get(), 1)) != DMRG_OK) return bail(st);
   }
-  *out = hp;
+  *out = h.release();
+  return DMRG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                             int64_t n_terms, const dmrg_term* terms, const double* left_pool,
+                             int64_t left_pool_len, const double* right_pool,
+                             int64_t right_pool_len, dmrg_prec prec, dmrg_heff_t* out) {
+  return heff_create(ctx, L, R, Q, n_terms, terms, left_pool, left_pool_len, right_pool,
+                     right_pool_len, prec, -1, out);
+}
+
+dmrg_status dmrg_heff_create_streamed(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
+                                      const int32_t Q[2], int64_t n_terms, const dmrg_term* terms,
+                                      const double* left_pool_host, int64_t left_pool_len,
+                                      const double* right_pool_host, int64_t right_pool_len,
+                                      dmrg_prec prec, int64_t device_bytes, dmrg_heff_t* out) {
+  if (out) *out = nullptr;
+  if (device_bytes < 0) return fail(DMRG_EINVAL, "heff_create_streamed: negative device budget");
+  return heff_create(ctx, L, R, Q, n_terms, terms, left_pool_host, left_pool_len, right_pool_host,
+                     right_pool_len, prec, device_bytes, out);
+}
+
+dmrg_status dmrg_heff_stream_info(dmrg_heff_t h, int64_t* resident_bytes, int64_t* streamed_bytes,
+                                  int32_t* resident_waves, int32_t* streamed_waves) {
+  if (!h) return fail(DMRG_EINVAL, "heff_stream_info: h is NULL");
+  const StreamPlan& S = h->strm;
+  if (resident_bytes) *resident_bytes = 8 * S.cache_elems;
+  if (streamed_bytes) *streamed_bytes = 8 * S.streamed_elems;
+  if (streamed_waves) *streamed_waves = S.n_streamed;
+  if (resident_waves) *resident_waves = (int32_t)S.waves.size() - S.n_streamed;
   return DMRG_OK;
 }
 
@@ -683,6 +755,7 @@ void dmrg_heff_destroy(dmrg_heff_t h) {
   if (h->adj_part) (void)hipFree(h->adj_part);
   if (h->d_dblocks) (void)hipFree(h->d_dblocks);
   if (h->d_ditems) (void)hipFree(h->d_ditems);
+  h->strm.release();
   delete h;
 }
 
@@ -697,6 +770,8 @@ dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec) {
 
 dmrg_status dmrg_heff_set_persistent(dmrg_heff_t h, int32_t enable) {
   if (!h) return fail(DMRG_EINVAL, "set_persistent: h is NULL");
+  if (enable && h->strm.on)
+    return fail(DMRG_ENOTSUP, "set_persistent: the out-of-core form runs wave by wave");
   if (enable && !h->pers.built) {
     dmrg_status st = h->pers.build(h->fwdp[0]);
     if (st != DMRG_OK) return st;
@@ -726,6 +801,8 @@ int64_t dmrg_heff_workspace_bytes(dmrg_heff_t h) {
 
 dmrg_status dmrg_heff_use_graph(dmrg_heff_t h, int32_t enable) {
   if (!h) return fail(DMRG_EINVAL, "use_graph: h is NULL");
+  if (enable && h->strm.on)
+    return fail(DMRG_ENOTSUP, "use_graph: the out-of-core form is not captured in a graph");
   h->use_graph = enable ? 1 : 0;
   if (!enable) free_graph(h);
   return DMRG_OK;
@@ -798,6 +875,7 @@ dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kern
 
 dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y, float* ms) {
   if (!h || !psi || !y || !ms) return fail(DMRG_EINVAL, "heff_apply_profiled: bad arguments");
+  if (h->strm.on) return fail(DMRG_ENOTSUP, "heff_apply_profiled: not for the out-of-core form");
   hipStream_t s = h->ctx->stream;
   const auto& P = h->fwd();
   const size_t n = P.launches.size();
@@ -832,14 +910,19 @@ dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y
 
 dmrg_status dmrg_heff_diag(dmrg_heff_t h, double* diag) {
   if (!h || !diag) return fail(DMRG_EINVAL, "heff_diag: bad arguments");
-  return launch_diag(h->d_dblocks, h->n_dblocks, h->d_ditems, h->lpool, h->rpool, diag,
-                     h->max_block_elems, h->ctx->stream);
+  // out-of-core form: both tables index the compact device array of diagonals
+  const double* lp = h->strm.on ? h->strm.diag : h->lpool;
+  const double* rp = h->strm.on ? h->strm.diag : h->rpool;
+  return launch_diag(h->d_dblocks, h->n_dblocks, h->d_ditems, lp, rp, diag, h->max_block_elems,
+                     h->ctx->stream);
 }
 
 dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const double* ybar,
                                     double* psibar, double* left_pool_bar,
                                     double* right_pool_bar) {
   if (!h || !psi || !ybar) return fail(DMRG_EINVAL, "heff_apply_adjoint: bad arguments");
+  if (h->strm.on)
+    return fail(DMRG_ENOTSUP, "heff_apply_adjoint: needs the pools in device memory (not the out-of-core form)");
   if (!psibar && !left_pool_bar && !right_pool_bar) return DMRG_OK;
   const int want = (psibar ? 1 : 0) | (left_pool_bar ? 2 : 0) | (right_pool_bar ? 4 : 0);
   if (!h->adj_built || h->adj_mask != want) {
@@ -902,6 +985,7 @@ dmrg_status dmrg_heff_apply_adjoint(dmrg_heff_t h, const double* psi, const doub
 
 extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps) {
   if (!h || !psi || !y || reps < 1 || psi == y) return fail(DMRG_EINVAL, "heff_autotune: bad arguments");
+  if (h->strm.on) return fail(DMRG_ENOTSUP, "heff_autotune: not for the out-of-core form");
   hipStream_t s = h->ctx->stream;
   const int which = dmrg_heff_s::prog_index(h->prec);
   const Program& P = h->fwdp[which];

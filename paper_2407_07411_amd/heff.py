@@ -80,16 +80,30 @@ def wfn_layout(L: Basis, R: Basis, Q):
     return int(nb.value), offs, int(total.value)
 
 
+def _pinned_f64(t, name):
+    if not (isinstance(t, torch.Tensor) and t.device.type == "cpu" and t.is_pinned()
+            and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 tensor in pinned host memory")
+    return t
+
+
 class Heff:
     """H_eff of one two-site step: sector tables, operator-pair terms and the
-    two device pools (borrowed: they must stay alive and on the device)."""
+    two operator pools (borrowed: they must stay alive and unchanged).
 
-    def __init__(self, ctx: Context, Lq, Ld, Rq, Rd, Q, terms, left_pool, right_pool, prec=FP64):
+    device_bytes=None: the pools are device tensors.  Otherwise they are
+    pinned host tensors (out-of-core form) and device_bytes bounds the device
+    memory for their blocks: what fits is copied once, the rest is streamed
+    through two staging slots on every apply."""
+
+    def __init__(self, ctx: Context, Lq, Ld, Rq, Rd, Q, terms, left_pool, right_pool, prec=FP64,
+                 device_bytes=None):
         self.ctx = ctx
         self.L = Basis(ctx, Lq, Ld)
         self.R = Basis(ctx, Rq, Rd)
-        self.left_pool = _dev_f64(left_pool, "left_pool")
-        self.right_pool = _dev_f64(right_pool, "right_pool")
+        conv = _dev_f64 if device_bytes is None else _pinned_f64
+        self.left_pool = conv(left_pool, "left_pool")
+        self.right_pool = conv(right_pool, "right_pool")
         nL, nR = len(self.L.dim), len(self.R.dim)
         arr = (Term * max(1, len(terms)))()
         keep = []
@@ -111,9 +125,15 @@ class Heff:
         self.Q = (int(Q[0]), int(Q[1]))
         ctx.sync_stream()
         h = c_void_p()
-        check(lib().dmrg_heff_create(ctx.h, self.L.h, self.R.h, q, len(terms), arr,
-                                     _ptr(self.left_pool), self.left_pool.numel(),
-                                     _ptr(self.right_pool), self.right_pool.numel(), int(prec), byref(h)))
+        if device_bytes is None:
+            check(lib().dmrg_heff_create(ctx.h, self.L.h, self.R.h, q, len(terms), arr,
+                                         _ptr(self.left_pool), self.left_pool.numel(),
+                                         _ptr(self.right_pool), self.right_pool.numel(), int(prec), byref(h)))
+        else:
+            check(lib().dmrg_heff_create_streamed(ctx.h, self.L.h, self.R.h, q, len(terms), arr,
+                                                  _ptr(self.left_pool), self.left_pool.numel(),
+                                                  _ptr(self.right_pool), self.right_pool.numel(), int(prec),
+                                                  int(device_bytes), byref(h)))
         self.h = h
         self._destroy = lib().dmrg_heff_destroy
         self.size = int(lib().dmrg_heff_size(h))
@@ -125,6 +145,13 @@ class Heff:
         if getattr(self, "h", None) and fn is not None:
             fn(self.h)
             self.h = None
+
+    def stream_info(self):
+        """(resident bytes, bytes streamed per apply, resident waves, streamed
+        waves) of the out-of-core form; zeros for device pools."""
+        rb, sb, rw, sw = c_int64(), c_int64(), c_int32(), c_int32()
+        check(lib().dmrg_heff_stream_info(self.h, byref(rb), byref(sb), byref(rw), byref(sw)))
+        return int(rb.value), int(sb.value), int(rw.value), int(sw.value)
 
     def set_precision(self, prec):
         check(lib().dmrg_heff_set_precision(self.h, int(prec)))
