@@ -96,7 +96,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (tile shapes per size class, per-phase or persistent launch)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the off-path measurements (SVD truncation, adjoint at L=24)")
+                    help="skip the off-path measurements (SVD truncation, out-of-core matvec, adjoint at L=24, sweeps)")
+    ap.add_argument("--only-out-of-core", action="store_true",
+                    help="run only the out-of-core matvec measurement and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device twice, by the runtime's copy and by an "
                          "elementwise kernel (reference dispatches for HBM byte counters)")
@@ -121,6 +123,9 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only_out_of_core:
+        print(json.dumps(dict(workload=args.workload, out_of_core=streamed_timing(dev, w))), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -173,6 +178,10 @@ def main():
         kid0, _ = h.launches()
         form = "persistent" if len(kid0) == 1 and int(kid0[0]) == 64 else "per_phase"
         log(f"matvec form: {form}")
+        # marker for kernel traces: the dispatches between this spin kernel
+        # and the next are the kept plan's matvecs and Davidson iterations
+        # (the tuner before it launches the same kernels on subsets)
+        torch.cuda._sleep(1000)
 
         # ---- matvec alone (FP64): warm-up, then HIP events on this stream
         for _ in range(2):
@@ -284,6 +293,7 @@ def main():
         extra.update(matvec_ms_fp32=round(f32_ms, 3), matvec_tflops_fp32=round(flops / f32_ms / 1e9, 3),
                      fp32_speedup=round(mv_ms / f32_ms, 3), fp32_matvec_rel_err=f32_err)
         log(f"matvec fp32 {f32_ms:.2f} ms -> {flops/f32_ms/1e9:.2f} TFLOPS (FP64-equivalent), rel err {f32_err:.2e}")
+        torch.cuda._sleep(1000)  # end marker of the measured matvecs for kernel traces
 
         # ---- Davidson to the 1e-6 residual from the lowest diagonal element
         ground = None
@@ -330,6 +340,9 @@ def main():
             log(f"svd truncation: {svd_s:.3f} s, kept {int(np.sum(kept))}, error {terr:.3e}")
             del U, S, Vt
     if not args.no_extra:
+        del h  # its workspace; the pools stay for the CPU baseline
+        torch.cuda.empty_cache()
+        extra["out_of_core_" + args.workload] = streamed_timing(dev, w)
         extra["adjoint_l24_d1024"] = adjoint_timing(dev)
         # the L=24, D=1024 single FP64 matvec with all 1226 terms, on its own
         extra["matvec_tflops_l24_d1024_all_terms"] = extra["adjoint_l24_d1024"]["forward_tflops"]
@@ -393,6 +406,81 @@ def adjoint_timing(dev):
                adjoint_over_forward=round(adj_ms / fwd_ms, 3),
                adjoint_outputs="psi-bar, left-pool and right-pool gradients")
     log("adjoint l24_d1024:", out)
+    return out
+
+
+def streamed_timing(dev, w, pool_gb=24.0):
+    """The out-of-core form on the same workload with pools capped to
+    pool_gb: the pools in pinned host memory, a device budget of 75% of them
+    (the blocks that fit copied once, the rest streamed through two slots
+    per matvec) and a budget of 8 GB with nothing resident.  Each matvec is
+    timed with HIP events and compared with the plan over device pools; the
+    bound is the larger of that plan's time and the streamed bytes at the
+    measured pinned host-to-device rate."""
+    import os
+
+    import torch
+
+    from paper_2407_07411_amd import heff as H
+    from synth.problem import make_problem
+    prob = make_problem(w["L"], w["n_elec"], w["two_sz"], w["D"], w["seed"], device=dev,
+                        pool_budget_bytes=int(pool_gb * 1e9))
+    pb = prob.meta["pool_bytes"]
+    lp = torch.empty(prob.left_pool.numel(), dtype=torch.float64, pin_memory=True)
+    rp = torch.empty(prob.right_pool.numel(), dtype=torch.float64, pin_memory=True)
+    lp.copy_(prob.left_pool)
+    rp.copy_(prob.right_pool)
+    stream = torch.cuda.Stream(dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps=3):
+        fn()
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    out = dict(pool_gb=round(pb / 1e9, 3), terms=prob.meta["n_terms"])
+    with torch.cuda.stream(stream):
+        n = min(lp.numel(), 1 << 29)
+        dst = torch.empty(n, dtype=torch.float64, device=dev)
+        h2d_ms = timed(lambda: dst.copy_(lp[:n], non_blocking=True))
+        h2d = n * 8 / h2d_ms / 1e6
+        del dst
+        ctx = H.Context(0)
+        x = prob.psi.clone()
+        h = H.Heff(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, prob.terms, prob.left_pool, prob.right_pool)
+        flops, _ = h.flops()
+        y_ref = h.apply(x)
+        dev_ms = timed(lambda: h.apply(x, y_ref))
+        del h
+        prob.left_pool = prob.right_pool = None
+        torch.cuda.empty_cache()
+        out.update(h2d_gbps=round(h2d, 2), device_pools_matvec_ms=round(dev_ms, 3),
+                   device_pools_tflops=round(flops / dev_ms / 1e9, 3))
+        for label, dbytes, resident_kb in (("budget_75pct", int(0.75 * pb), None), ("budget_8gb_all_streamed",
+                                                                                     int(8e9), "0")):
+            if resident_kb is None:
+                os.environ.pop("DMRG_HEFF_STREAM_RESIDENT_KB", None)
+            else:
+                os.environ["DMRG_HEFF_STREAM_RESIDENT_KB"] = resident_kb
+            hs = H.Heff(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, prob.terms, lp, rp, device_bytes=dbytes)
+            os.environ.pop("DMRG_HEFF_STREAM_RESIDENT_KB", None)
+            rb, sb, rw, sw = hs.stream_info()
+            y = torch.empty_like(x)
+            ms = timed(lambda: hs.apply(x, y))
+            err = float(torch.linalg.vector_norm(y - y_ref) / torch.linalg.vector_norm(y_ref))
+            bound = max(dev_ms, sb / h2d / 1e6)
+            out[label] = dict(device_gb=round(dbytes / 1e9, 3), resident_gb=round(rb / 1e9, 3),
+                              streamed_gb_per_matvec=round(sb / 1e9, 3), resident_waves=rw, streamed_waves=sw,
+                              matvec_ms=round(ms, 3), pcie_inclusive_tflops=round(flops / ms / 1e9, 3),
+                              bound_ms=round(bound, 3), frac_of_bound=round(bound / ms, 4),
+                              rel_err_vs_device_pools=err)
+            del hs
+    log("out-of-core:", out)
     return out
 
 

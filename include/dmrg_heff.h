@@ -139,8 +139,8 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
  * of them is copied to the device once).  device_bytes bounds the device memory that
  * holds operator blocks (the workspace of dmrg_heff_create comes on top):
  * when every distinct block fits, all are copied once at creation;
- * otherwise two staging slots (DMRG_HEFF_STREAM_SLOT_KB, else a quarter of
- * the budget, at most 4 GiB, at least the largest pair's blocks) are set
+ * otherwise two staging slots (DMRG_HEFF_STREAM_SLOT_KB, else 1/16 of the
+ * budget, at most 1 GiB, at least the largest pair's blocks) are set
  * aside, the items whose blocks fit the rest are copied once, and every
  * apply copies the remaining blocks slot by slot on a copy stream while the
  * compute stream runs the resident items and the slot filled before.
@@ -222,11 +222,13 @@ dmrg_status dmrg_heff_check(dmrg_heff_t h);
  * the split kernels skip 256x128) on the plan's
  * own problems, grouped by phase (intermediates / output sums) and by the
  * (M, N) size class (<=16, 32, 64, 128, 256, 512, larger), keeps the fastest
- * shape per group and rebuilds the plan with it.  The timing runs the
+ * shape per group and rebuilds the plan with it, keeping the rebuilt plan
+ * only when its whole matvec beats the previous plan's (a phase runs its
+ * shapes side by side, which per-group timing does not see).  The timing runs the
  * current precision's kernels on the context stream with psi and y (device
  * double[size]; y and the workspace are overwritten).  reps >= 1 timed
  * launches per candidate.  The adjoint keeps the built-in rule.  For FP64
- * it then times the rebuilt matvec as per-phase launches and as the single
+ * it then times the kept matvec as per-phase launches and as the single
  * persistent launch (dmrg_heff_set_persistent) and keeps the faster form.
  * Synchronises. */
 dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps);
@@ -240,9 +242,12 @@ dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int3
  * FP32-operand kernels; 32: the ordered reduction of cut K sums) and its
  * algorithmic FLOPs (2 M N K summed over its problems, 0 for reductions). */
 dmrg_status dmrg_heff_launches(dmrg_heff_t h, int64_t* n_launches, int32_t* kernel, double* flops);
-/* y = H_eff psi as dmrg_heff_apply (eager), bracketing every launch with HIP
- * events on the context stream; ms (host float[n_launches]) receives each
- * launch's duration.  Synchronises the stream. */
+/* y = H_eff psi as dmrg_heff_apply (eager, the same launch schedule: largest
+ * tile shape of a phase on the context stream, smaller shapes and
+ * reductions beside it on side streams), bracketing every launch with HIP
+ * events on the stream it runs on; ms (host float[n_launches]) receives each
+ * launch's duration.  Synchronises the stream.  DMRG_ENOTSUP for the
+ * out-of-core form. */
 dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y, float* ms);
 
 /* ---- Davidson -------------------------------------------------------------- */

@@ -154,27 +154,22 @@ dmrg_status Program::run(const Bases& b, hipStream_t s, int precision) const {
   return run_range(b, s, precision, 0, launches.size());
 }
 
-dmrg_status Program::run_range(const Bases& b, hipStream_t s, int precision, size_t l0, size_t l1) const {
-  if (concurrent && s != nullptr) return run_concurrent(b, s, precision, l0, l1);
-  for (size_t i = l0; i < l1; ++i) {
-    const Launch& l = launches[i];
-    Launch x = l;
-    x.split = precision;
-    dmrg_status st = l.cfg == CFG_REDUCE ? launch_reduce(x, b, d_reds, d_red_parts, s)
-                                         : launch_gemm(x, b, d_probs, d_segs, d_tiles, s);
-    if (st != DMRG_OK) return st;
-  }
-  return DMRG_OK;
+dmrg_status Program::launch_at(size_t i, const Bases& b, hipStream_t s, int precision) const {
+  Launch x = launches[i];
+  x.split = precision;
+  if (prof_ev) DMRG_HIP(hipEventRecord(prof_ev[2 * i], s));
+  dmrg_status st = x.cfg == CFG_REDUCE ? launch_reduce(x, b, d_reds, d_red_parts, s)
+                                       : launch_gemm(x, b, d_probs, d_segs, d_tiles, s);
+  if (st == DMRG_OK && prof_ev) DMRG_HIP(hipEventRecord(prof_ev[2 * i + 1], s));
+  return st;
 }
 
-namespace {
-dmrg_status launch_one(const Launch& l, const Bases& b, const Program& P, hipStream_t s, int precision) {
-  Launch x = l;
-  x.split = precision;
-  return l.cfg == CFG_REDUCE ? launch_reduce(x, b, P.d_reds, P.d_red_parts, s)
-                             : launch_gemm(x, b, P.d_probs, P.d_segs, P.d_tiles, s);
+dmrg_status Program::run_range(const Bases& b, hipStream_t s, int precision, size_t l0, size_t l1) const {
+  if (concurrent && s != nullptr) return run_concurrent(b, s, precision, l0, l1);
+  for (size_t i = l0; i < l1; ++i)
+    if (dmrg_status st = launch_at(i, b, s, precision); st != DMRG_OK) return st;
+  return DMRG_OK;
 }
-}  // namespace
 
 // Stream s (the caller's) runs the largest tile shape of every phase; side[0]
 // runs the smaller shapes of the same phase (fork after the previous phase,
@@ -208,17 +203,17 @@ dmrg_status Program::run_concurrent(const Bases& b, hipStream_t s, int precision
       DMRG_HIP(hipEventRecord(fork, s));
       DMRG_HIP(hipStreamWaitEvent(side[0], fork, 0));
       for (size_t k = 1; k < gemms.size(); ++k) {
-        dmrg_status st = launch_one(*gemms[k], b, *this, side[0], precision);
+        dmrg_status st = launch_at(gemms[k] - launches.data(), b, side[0], precision);
         if (st != DMRG_OK) return st;
       }
       DMRG_HIP(hipEventRecord(done, side[0]));
       if (!gemms.empty()) {
-        dmrg_status st = launch_one(*gemms[0], b, *this, s, precision);
+        dmrg_status st = launch_at(gemms[0] - launches.data(), b, s, precision);
         if (st != DMRG_OK) return st;
       }
       DMRG_HIP(hipStreamWaitEvent(s, done, 0));
     } else if (!gemms.empty()) {
-      dmrg_status st = launch_one(*gemms[0], b, *this, s, precision);
+      dmrg_status st = launch_at(gemms[0] - launches.data(), b, s, precision);
       if (st != DMRG_OK) return st;
     }
     if (red) {
@@ -231,13 +226,13 @@ dmrg_status Program::run_concurrent(const Bases& b, hipStream_t s, int precision
         hipEvent_t fork = events[ev++], done = events[ev++];
         DMRG_HIP(hipEventRecord(fork, s));
         DMRG_HIP(hipStreamWaitEvent(side[1], fork, 0));
-        dmrg_status st = launch_one(*red, b, *this, side[1], precision);
+        dmrg_status st = launch_at(red - launches.data(), b, side[1], precision);
         if (st != DMRG_OK) return st;
         DMRG_HIP(hipEventRecord(done, side[1]));
         pending = done;
         pending_phase = ph;
       } else {
-        dmrg_status st = launch_one(*red, b, *this, s, precision);
+        dmrg_status st = launch_at(red - launches.data(), b, s, precision);
         if (st != DMRG_OK) return st;
       }
     }

@@ -156,6 +156,10 @@ struct Program {
   // reduction runs beside the next phase when that one writes intermediates
   // only.  Needs a non-null caller stream; otherwise launches run in order.
   bool concurrent = false;
+  // When set, run() records prof_ev[2i] / prof_ev[2i + 1] around launch i on
+  // the stream that launch goes to (per-launch durations of the real schedule).
+  mutable const hipEvent_t* prof_ev = nullptr;
+  dmrg_status launch_at(size_t i, const Bases& b, hipStream_t s, int precision) const;
   mutable hipStream_t side[2] = {nullptr, nullptr};
   mutable std::vector<hipEvent_t> events;
   dmrg_status run_concurrent(const Bases& b, hipStream_t s, int precision, size_t l0, size_t l1) const;

@@ -878,30 +878,28 @@ dmrg_status dmrg_heff_apply_profiled(dmrg_heff_t h, const double* psi, double* y
   if (h->strm.on) return fail(DMRG_ENOTSUP, "heff_apply_profiled: not for the out-of-core form");
   hipStream_t s = h->ctx->stream;
   const auto& P = h->fwd();
-  const size_t n = P.launches.size();
-  std::vector<hipEvent_t> ev(n + 1, nullptr);
+  const bool pers = h->persistent && h->prec == DMRG_FP64;
+  const size_t n = pers ? 1 : P.launches.size();
+  // two events per launch, recorded on the stream each launch runs on, so
+  // the durations are those of the matvec's own schedule
+  std::vector<hipEvent_t> ev(2 * n, nullptr);
   dmrg_status st = DMRG_OK;
-  for (size_t i = 0; i <= n && st == DMRG_OK; ++i)
+  for (size_t i = 0; i < ev.size() && st == DMRG_OK; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) st = fail(DMRG_EHIP, "hipEventCreate failed");
   const Bases b = fwd_bases(h, psi, y);
   if (st == DMRG_OK) st = fwd_prologue(h, psi, b);
-  if (st == DMRG_OK && hipEventRecord(ev[0], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
-  const bool pers = h->persistent && h->prec == DMRG_FP64;
   if (pers && st == DMRG_OK) {
-    st = h->pers.run(b, P, s, h->spin_limit);
+    if (hipEventRecord(ev[0], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
+    if (st == DMRG_OK) st = h->pers.run(b, P, s, h->spin_limit);
     if (st == DMRG_OK && hipEventRecord(ev[1], s) != hipSuccess) st = fail(DMRG_EHIP, "hipEventRecord failed");
-  }
-  for (size_t i = 0; i < n && st == DMRG_OK && !pers; ++i) {
-    Launch x = P.launches[i];
-    x.split = h->prec;
-    st = x.cfg == CFG_REDUCE ? launch_reduce(x, b, P.d_reds, P.d_red_parts, s)
-                             : launch_gemm(x, b, P.d_probs, P.d_segs, P.d_tiles, s);
-    if (st == DMRG_OK && hipEventRecord(ev[i + 1], s) != hipSuccess)
-      st = fail(DMRG_EHIP, "hipEventRecord failed");
+  } else if (st == DMRG_OK) {
+    P.prof_ev = ev.data();
+    st = P.run(b, s, h->prec);
+    P.prof_ev = nullptr;
   }
   if (st == DMRG_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(DMRG_EHIP, "hipStreamSynchronize failed");
-  for (size_t i = 0; i < (pers ? 1 : n) && st == DMRG_OK; ++i)
-    if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess)
+  for (size_t i = 0; i < n && st == DMRG_OK; ++i)
+    if (hipEventElapsedTime(&ms[i], ev[2 * i], ev[2 * i + 1]) != hipSuccess)
       st = fail(DMRG_EHIP, "hipEventElapsedTime failed");
   for (auto e : ev)
     if (e) (void)hipEventDestroy(e);
@@ -1063,6 +1061,7 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
   }
   cleanup();
   // rebuild the forward program with the chosen shapes
+  const TuneTable prev = h->tune[which];
   h->tune[which] = table;
   Program old = std::move(h->fwdp[which]);
   h->fwdp[which] = Program();
@@ -1078,28 +1077,59 @@ extern "C" dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, doub
   if (st != DMRG_OK) {
     h->fwdp[which].release();
     h->fwdp[which] = std::move(old);
+    h->tune[which] = prev;
     return st;
   }
-  old.release();
   free_graph(h);
-  if (which != 0) return DMRG_OK;
-  // FP64: the per-phase launches or the single persistent launch, whichever
-  // runs the rebuilt program faster (the two give identical results)
-  if ((st = h->pers.build(h->fwdp[0])) != DMRG_OK) return st;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
     if (t0) (void)hipEventDestroy(t0);
+    old.release();
     return fail(DMRG_EHIP, "heff_autotune: hipEventCreate failed");
+  }
+  // whole matvec (per-phase launches), after one warm-up
+  auto time_matvec = [&](float* out) {
+    dmrg_status r = heff_apply_eager(h, psi, y);
+    if (r == DMRG_OK && hipEventRecord(t0, s) != hipSuccess) r = fail(DMRG_EHIP, "event");
+    for (int k = 0; k < reps && r == DMRG_OK; ++k) r = heff_apply_eager(h, psi, y);
+    if (r == DMRG_OK && hipEventRecord(t1, s) != hipSuccess) r = fail(DMRG_EHIP, "event");
+    if (r == DMRG_OK && hipEventSynchronize(t1) != hipSuccess) r = fail(DMRG_EHIP, "event sync");
+    if (r == DMRG_OK && hipEventElapsedTime(out, t0, t1) != hipSuccess) r = fail(DMRG_EHIP, "elapsed");
+    return r;
+  };
+  // the groups were timed one at a time, but a matvec runs the shapes of a
+  // phase side by side: keep the rebuilt program only if the whole product
+  // is faster than the one it replaces
+  const int was_persistent = h->persistent;
+  h->persistent = 0;
+  float t_new = 0.f, t_old = 0.f;
+  st = time_matvec(&t_new);
+  std::swap(h->fwdp[which], old);
+  if (st == DMRG_OK) st = time_matvec(&t_old);
+  if (st == DMRG_OK && t_new < t_old) {
+    std::swap(h->fwdp[which], old);  // the rebuilt program
+  } else {
+    h->tune[which] = prev;           // the previous program stays
+  }
+  old.release();
+  if (st != DMRG_OK || which != 0) {
+    h->persistent = which == 0 ? 0 : was_persistent;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (st == DMRG_OK && was_persistent && h->prec == DMRG_FP64) st = h->pers.build(h->fwdp[0]);
+    return st;
+  }
+  // FP64: the per-phase launches or the single persistent launch, whichever
+  // runs the kept program faster (the two give identical results)
+  if ((st = h->pers.build(h->fwdp[0])) != DMRG_OK) {
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return st;
   }
   float best[2] = {0.f, 0.f};
   for (int mode = 0; mode < 2 && st == DMRG_OK; ++mode) {
     h->persistent = mode;
-    st = heff_apply_eager(h, psi, y);  // warm-up
-    if (st == DMRG_OK && hipEventRecord(t0, s) != hipSuccess) st = fail(DMRG_EHIP, "event");
-    for (int r = 0; r < reps && st == DMRG_OK; ++r) st = heff_apply_eager(h, psi, y);
-    if (st == DMRG_OK && hipEventRecord(t1, s) != hipSuccess) st = fail(DMRG_EHIP, "event");
-    if (st == DMRG_OK && hipEventSynchronize(t1) != hipSuccess) st = fail(DMRG_EHIP, "event sync");
-    if (st == DMRG_OK && hipEventElapsedTime(&best[mode], t0, t1) != hipSuccess) st = fail(DMRG_EHIP, "elapsed");
+    st = time_matvec(&best[mode]);
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);

@@ -30,15 +30,17 @@ namespace dmrg {
 
 namespace {
 
-// Staging slot size: DMRG_HEFF_STREAM_SLOT_KB, else a quarter of the device
-// budget, at most 4 GiB (doubles; raised to the largest item's blocks by the
-// caller).
+// Staging slot size: DMRG_HEFF_STREAM_SLOT_KB, else 1/16 of the device
+// budget, at most 1 GiB (doubles; raised to the largest item's blocks by the
+// caller).  Small slots leave more of the budget to resident blocks (every
+// byte resident is a byte not copied per matvec); 1 GiB of operator blocks
+// still holds thousands of output tiles at the paper's bond dimensions.
 int64_t slot_doubles(int64_t budget) {
   if (const char* s = std::getenv("DMRG_HEFF_STREAM_SLOT_KB")) {
     const int64_t kb = std::atoll(s);
     if (kb >= 1) return kb * 1024 / 8;
   }
-  return std::min<int64_t>(budget / 4, (int64_t)1 << 29);
+  return std::min<int64_t>(budget / 16, (int64_t)1 << 27);
 }
 
 // DMRG_HEFF_STREAM_RESIDENT_KB caps the resident copy below what the budget
@@ -206,21 +208,10 @@ dmrg_status build_stream_plan(dmrg_heff_s* h, int64_t device_bytes) {
     }
   }
   const int64_t wb = std::max(h->work_budget, ni ? *std::max_element(need.begin(), need.end()) : 0);
-  // waves: resident ones by workspace, streamed ones by workspace and slot
+  // waves: streamed ones by workspace and slot; resident ones by workspace
+  // and, when there are streamed waves, in about as many pieces of equal
+  // FLOPs, so that every streamed wave has resident work to overlap with
   std::vector<StreamWave> res, str;
-  {
-    size_t w0 = 0;
-    int64_t used = 0;
-    for (size_t i = 0; i < r; ++i) {
-      if (used + need[i] > wb && i > w0) {
-        res.push_back(StreamWave{w0, i, -1, 0, 0, 0});
-        w0 = i;
-        used = 0;
-      }
-      used += need[i];
-    }
-    if (r > 0 || ni == 0) res.push_back(StreamWave{w0, r, -1, 0, 0, 0});
-  }
   {
     size_t w0 = r;
     int64_t used = 0;
@@ -245,6 +236,25 @@ dmrg_status build_stream_plan(dmrg_heff_s* h, int64_t device_bytes) {
       used += need[i];
     }
     if (r < ni) str.push_back(StreamWave{w0, ni, 0, 0, 0, 0});
+  }
+  {
+    double res_flops = 0.0;
+    for (size_t i = 0; i < r; ++i) res_flops += flops[i];
+    const double piece = str.empty() ? 0.0 : res_flops / (double)str.size();
+    size_t w0 = 0;
+    int64_t used = 0;
+    double acc = 0.0;
+    for (size_t i = 0; i < r; ++i) {
+      if ((used + need[i] > wb || (piece > 0.0 && acc + 0.5 * flops[i] > piece)) && i > w0) {
+        res.push_back(StreamWave{w0, i, -1, 0, 0, 0});
+        w0 = i;
+        used = 0;
+        acc = 0.0;
+      }
+      used += need[i];
+      acc += flops[i];
+    }
+    if (r > 0 || ni == 0) res.push_back(StreamWave{w0, r, -1, 0, 0, 0});
   }
   // buffers: one resident copy, each streamed wave laid out in its slot
   S.aoff.assign(ni, -1);
