@@ -287,11 +287,15 @@ typedef struct {
  * (2 * max_subspace + 2 * restart_keep + 5) * size doubles. */
 dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts,
                                  const double* psi0, dmrg_dav_t* out);
-/* One iteration: Rayleigh-Ritz on the current subspace, residual, and (when
- * not converged) correction, orthogonalisation and one matvec.  Synchronises
- * the stream to read the residual.  Returns DMRG_OK while iterating or once
- * converged (res->converged), DMRG_ENOCONV when max_iter is exhausted or the
- * correction vanished. */
+/* One iteration.  The first call: Rayleigh-Ritz on the start subspace and
+ * its residual.  Every later call: the correction of the previous Ritz pair
+ * (restart when the subspace is full, preconditioner, orthogonalisation,
+ * one matvec), then Rayleigh-Ritz and the residual on the grown subspace,
+ * as one launch sequence (one hipGraph with opts->use_graph) and one
+ * synchronisation to read the residual.  Returns DMRG_OK while iterating or
+ * once converged (res->converged; later calls return DMRG_EINVAL),
+ * DMRG_ENOCONV when max_iter is exhausted or the correction vanished (then
+ * res and the Ritz vector stay those of the last complete iteration). */
 dmrg_status dmrg_davidson_step(dmrg_dav_t d, dmrg_dav_result* res);
 /* Copy the current Ritz vector (unit norm) to x (device double[size]). */
 dmrg_status dmrg_davidson_vector(dmrg_dav_t d, double* x);

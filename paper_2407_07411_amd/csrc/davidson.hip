@@ -15,8 +15,14 @@
 //            Gram-Schmidt, normalisation, the matvec w = H t, and the update
 //            of V, W, G and k.
 //
-// The host reads the small status record after stage A and stops when the
-// residual reaches the tolerance.
+// The first step runs stage A alone; every later step is ONE launch
+// sequence (one graph) of stage B followed by the next stage A, so an
+// iteration costs one graph launch and one host synchronisation: the host
+// reads the small status record at the end and stops when the residual
+// reaches the tolerance.  When stage B's correction vanishes (the stall
+// flag), the update of V, W, G and k and the whole of the following stage A
+// skip on the device, so the state, the Ritz pair and the residual stay
+// those of the last complete iteration.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -109,6 +115,7 @@ __global__ __launch_bounds__(RED_THREADS) void finish_dot_kernel(const double* _
 // (row stride KMAX) in the same order, st->theta = lowest.
 __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ G, DavState* st,
                                                      double* __restrict__ Eout) {
+  if (st->stalled) return;  // the last correction vanished: keep the last Ritz pair
   __shared__ double A[KMAX][KMAX + 1];
   __shared__ double E[KMAX][KMAX + 1];
   __shared__ double cs[KMAX / 2][2];
@@ -215,6 +222,7 @@ __global__ __launch_bounds__(RED_THREADS) void ritz_kernel(const double* __restr
                                                            const DavState* st, int64_t n,
                                                            double* __restrict__ x, double* __restrict__ r,
                                                            double* __restrict__ partial) {
+  if (st->stalled) return;
   __shared__ double red[RED_THREADS];
   __shared__ double s[KMAX];
   const int k = st->k;
@@ -243,6 +251,7 @@ __global__ __launch_bounds__(RED_THREADS) void ritz_kernel(const double* __restr
 }
 
 __global__ void finish_res_kernel(const double* __restrict__ partial, int nblocks, DavState* st) {
+  if (st->stalled) return;
   __shared__ double red[RED_THREADS];
   double acc = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) acc += partial[(int64_t)b * KMAX];
@@ -325,6 +334,7 @@ __global__ void normalize_kernel(const double* __restrict__ dots, DavState* st, 
 // V[k] = t, W[k] = w
 __global__ void append_kernel(const double* __restrict__ t, const double* __restrict__ w,
                               const DavState* st, int64_t n, double* __restrict__ V, double* __restrict__ W) {
+  if (st->stalled) return;  // a vanished correction is not added to the subspace
   const int k = st->k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     V[(int64_t)k * n + e] = t[e];
@@ -334,6 +344,7 @@ __global__ void append_kernel(const double* __restrict__ t, const double* __rest
 
 // G[i][k] = G[k][i] = dots[i], i <= k; k += 1.
 __global__ void grow_kernel(const double* __restrict__ dots, DavState* st, double* __restrict__ G) {
+  if (st->stalled) return;
   const int k = st->k;
   for (int i = threadIdx.x; i <= k; i += blockDim.x) {
     G[i * KMAX + k] = dots[i];
@@ -467,7 +478,8 @@ struct dmrg_dav_s {
   DavState* host = nullptr;  // pinned
   int iters = 0, matvecs = 0, tail = 0;
   bool done = false;
-  hipGraphExec_t gA = nullptr, gB = nullptr;
+  bool started = false;  // stage A of the first step has run
+  hipGraphExec_t gA = nullptr, gB = nullptr;  // gB: stage B + stage A
   hipGraph_t grA = nullptr, grB = nullptr;
 };
 
@@ -534,6 +546,13 @@ dmrg_status stage_b(dmrg_dav_s* d, hipStream_t s) {
   normalize_kernel<<<g, 256, 0, s>>>(d->dots, d->st, d->n, d->t, 1e-12);
   DMRG_HIP(hipGetLastError());
   return expand(d, s);
+}
+
+// One iteration after the first: the correction and matvec, then the next
+// Ritz pair and the status record for the host.
+dmrg_status stage_ba(dmrg_dav_s* d, hipStream_t s) {
+  dmrg_status st = stage_b(d, s);
+  return st == DMRG_OK ? stage_a(d, s) : st;
 }
 
 void free_dav(dmrg_dav_s* d) {
@@ -652,10 +671,16 @@ dmrg_status dmrg_davidson_create(dmrg_heff_t h, const dmrg_dav_opts* opts, const
 
 dmrg_status dmrg_davidson_step(dmrg_dav_t d, dmrg_dav_result* res) {
   if (!d || !res) return fail(DMRG_EINVAL, "davidson_step: bad arguments");
+  if (d->done) return fail(DMRG_EINVAL, "davidson_step: the solve has converged");
   hipStream_t s = d->h->ctx->stream;
-  dmrg_status st = run_stage(d, &d->gA, &d->grA, stage_a);
+  const bool expand_first = d->started;
+  dmrg_status st = expand_first ? run_stage(d, &d->gB, &d->grB, stage_ba) : run_stage(d, &d->gA, &d->grA, stage_a);
   if (st != DMRG_OK) return st;
+  d->started = true;
+  if (expand_first) d->matvecs++;
   DMRG_HIP(hipStreamSynchronize(s));
+  // a vanished correction left the state (and res) at the last iteration
+  if (expand_first && d->host->stalled) return fail(DMRG_ENOCONV, "davidson: correction vanished");
   d->iters++;
   res->energy = d->host->theta;
   res->residual = d->host->res;
@@ -668,12 +693,6 @@ dmrg_status dmrg_davidson_step(dmrg_dav_t d, dmrg_dav_result* res) {
     return DMRG_OK;
   }
   if (d->iters > d->o.max_iter) return fail(DMRG_ENOCONV, "davidson: iteration limit reached");
-  st = run_stage(d, &d->gB, &d->grB, stage_b);
-  if (st != DMRG_OK) return st;
-  d->matvecs++;
-  DMRG_HIP(hipMemcpyAsync(&d->host->stalled, &d->st->stalled, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  DMRG_HIP(hipStreamSynchronize(s));
-  if (d->host->stalled) return fail(DMRG_ENOCONV, "davidson: correction vanished");
   return DMRG_OK;
 }
 

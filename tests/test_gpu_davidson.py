@@ -109,3 +109,50 @@ def test_davidson_step_api(ctx):
     L.dmrg_davidson_destroy(d)
     assert res.converged and last <= 1e-9
     assert abs(res.energy - e0) < 1e-8
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_step_stall_keeps_last_iteration(use_graph):
+    """A 21-dimensional problem with tolerance 0: once the subspace spans the
+    whole space the next correction vanishes.  The step that finds it (one
+    launch sequence: correction, matvec, Rayleigh-Ritz) reports
+    DMRG_ENOCONV and leaves the energy, the residual and the Ritz vector of
+    the last complete iteration, which by then is the exact ground state."""
+    import ctypes
+
+    from paper_2407_07411_amd import _lib
+    from paper_2407_07411_amd.heff import Context
+    print("case stall", use_graph, flush=True)
+    prob = tiny_problem(seed=1, D=4, pairs=2)
+    Hd = heff_dense(prob)
+    w, _ = np.linalg.eigh(Hd)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        ctx = Context(0)
+        h = gpu_heff(ctx, prob)
+        psi = prob.psi.to("cuda").clone()
+        L = _lib.lib()
+        opts = _lib.DavOpts(200, 24, 2, use_graph, 0.0, 0, 0)
+        d = ctypes.c_void_p()
+        _lib.check(L.dmrg_davidson_create(h.h, ctypes.byref(opts), ctypes.c_void_p(psi.data_ptr()),
+                                          ctypes.byref(d)))
+        res = _lib.DavResult()
+        history = []
+        st = 0
+        for _ in range(60):
+            st = L.dmrg_davidson_step(d, ctypes.byref(res))
+            if st != 0:
+                break
+            history.append((res.energy, res.residual, res.iters))
+        msg = L.dmrg_last_error().decode()
+        out = torch.empty_like(psi)
+        _lib.check(L.dmrg_davidson_vector(d, ctypes.c_void_p(out.data_ptr())))
+        torch.cuda.synchronize()
+        L.dmrg_davidson_destroy(d)
+    assert st == -5 and "vanished" in msg, (st, msg)
+    assert len(history) <= 23
+    assert (res.energy, res.residual, res.iters) == history[-1]
+    assert abs(res.energy - w[0]) < 1e-10
+    x = out.cpu().numpy()
+    assert np.linalg.norm(Hd @ x - w[0] * x) < 1e-8
