@@ -161,6 +161,61 @@ dmrg_status dmrg_heff_create_streamed(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis
  * resident and streamed waves (all zero for a plan over device pools). */
 dmrg_status dmrg_heff_stream_info(dmrg_heff_t h, int64_t* resident_bytes, int64_t* streamed_bytes,
                                   int32_t* resident_waves, int32_t* streamed_waves);
+/* ---- SU(2) spin-adapted form ----------------------------------------------
+ * The paper's DMRG is spin adapted; its bond dimensions count multiplets
+ * (Introduction; Performance assessment section; P450 section).  Here the
+ * bases hold sectors (N, 2j) (2j >= 0) with the number of multiplets as
+ * dim, and Q = (N, 2S) is the total particle number and spin.  Operators of
+ * spin rank k are stored as reduced blocks O[(N', j'), (N, j)] (row-major
+ * d(N', j') x d(N, j)) in the Wigner-Eckart convention
+ * <j' m'|T^k_q|j m> = <j m; k q | j' m'> O[...] (Condon-Shortley
+ * Clebsch-Gordan coefficients).  A term is the scalar
+ * coeff * sum_q (-1)^(k-q) O^L_q (x) O^R_{-q} (fermionic sign (-1)^N(left
+ * input) when odd); on the reduced wavefunction blocks it adds
+ *   Y[(a', c')] += coeff * s * W * O^L[a', a] Psi[(a, c)] O^R[c', c]^T,
+ *   W = (-1)^(j_a + j_c' + k + S) sqrt((2j_a' + 1)(2j_c' + 1))
+ *       { j_a' j_c' S ; j_c j_a k } (a Wigner 6j symbol),
+ * and hc = 1 also adds the transpose of every such contribution.  One-sided
+ * terms are scalars (two_k = 0, dn = 0). */
+typedef struct {
+  int32_t two_k;     /* 2 x spin rank of both operators                     */
+  int32_t dn;        /* particle-number change of the left operator; the    */
+                     /* right one changes it by -dn                          */
+  int32_t odd;       /* 1: fermion-odd pair (must equal |dn| mod 2)          */
+  int32_t hc;        /* 1: also apply the transpose of the term             */
+  int32_t one_sided; /* 0 two-sided, 1 left only, 2 right only              */
+  int32_t reserved;  /* must be 0                                            */
+  double coeff;
+  int64_t n_left, n_right;      /* stored blocks of each side               */
+  const int64_t* left_blocks;   /* host int64[n_left][3]: output sector,    */
+                                /* input sector, offset in left_pool        */
+  const int64_t* right_blocks;  /* host int64[n_right][3], right_pool       */
+} dmrg_term_su2;
+/* The weight W above for doubled spins (2j_a, 2j_c, 2j_a', 2j_c', 2k, 2S);
+ * 0 where a triangle rule fails.  Host only, pure: it needs no context and
+ * no device. */
+double dmrg_su2_weight(int32_t two_ja, int32_t two_jc, int32_t two_ja2, int32_t two_jc2, int32_t two_k,
+                       int32_t two_s);
+/* Reduced wavefunction layout of total Q = (N, 2S): one block per (left
+ * sector a, right sector c) with N_a + N_c = N and |j_a - j_c| <= S <=
+ * j_a + j_c, ordered by a then c, row-major d_a x d_c, contiguous.
+ * block_left / block_right (host int32[n]) and block_offset (host int64[n])
+ * may be NULL; call once with NULL to learn n_blocks. */
+dmrg_status dmrg_wfn_layout_su2(dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2], int64_t* n_blocks,
+                                int32_t* block_left, int32_t* block_right, int64_t* block_offset,
+                                int64_t* total);
+/* dmrg_heff_create for the SU(2) form: the same device pools, plan,
+ * precisions and calls (apply, diag, adjoint, Davidson, autotune,
+ * persistent launch; the pool gradients of the adjoint are those of the
+ * reduced blocks).  Errors: DMRG_EINVAL (bad flags, 2j < 0, sector index
+ * outside a basis), DMRG_EQN (a block that breaks N' - N = dn or the
+ * triangle rule of j, k, j'; a block outside its pool; a one-sided term that
+ * is not a scalar), DMRG_ENOMEM, DMRG_EHIP.  Synchronises the context
+ * stream. */
+dmrg_status dmrg_heff_create_su2(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                                 int64_t n_terms, const dmrg_term_su2* terms, const double* left_pool,
+                                 int64_t left_pool_len, const double* right_pool, int64_t right_pool_len,
+                                 dmrg_prec prec, dmrg_heff_t* out);
 void dmrg_heff_destroy(dmrg_heff_t h);
 dmrg_status dmrg_heff_set_precision(dmrg_heff_t h, dmrg_prec prec);
 /* Host, synchronous.  alg_flops: FP64-equivalent FLOPs of one matvec, every

@@ -19,6 +19,13 @@ class Term(ctypes.Structure):
                 ("right_off", POINTER(c_int64))]
 
 
+class TermSU2(ctypes.Structure):
+    _fields_ = [("two_k", c_int32), ("dn", c_int32), ("odd", c_int32), ("hc", c_int32),
+                ("one_sided", c_int32), ("reserved", c_int32), ("coeff", c_double),
+                ("n_left", c_int64), ("n_right", c_int64), ("left_blocks", POINTER(c_int64)),
+                ("right_blocks", POINTER(c_int64))]
+
+
 class DavOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_int32), ("max_subspace", c_int32), ("restart_keep", c_int32),
                 ("use_graph", c_int32), ("tol", c_double), ("fp64_tail", c_int32),
@@ -56,6 +63,11 @@ SIGNATURES = {
                                           POINTER(c_void_p)]),
     "dmrg_heff_stream_info": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
                                       POINTER(c_int32)]),
+    "dmrg_su2_weight": (c_double, [c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "dmrg_wfn_layout_su2": (c_int, [c_void_p, c_void_p, POINTER(c_int32), POINTER(c_int64), c_void_p, c_void_p,
+                                    c_void_p, POINTER(c_int64)]),
+    "dmrg_heff_create_su2": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_int64, POINTER(TermSU2),
+                                     c_void_p, c_int64, c_void_p, c_int64, c_int, POINTER(c_void_p)]),
     "dmrg_heff_destroy": (None, [c_void_p]),
     "dmrg_heff_set_precision": (c_int, [c_void_p, c_int]),
     "dmrg_heff_set_persistent": (c_int, [c_void_p, c_int32]),

@@ -119,6 +119,13 @@ struct StreamPlan {
 };
 
 dmrg_status heff_apply_eager(struct ::dmrg_heff_s* h, const double* psi, double* y);
+// SU(2) form (su2.hip): reduced-block layout of total (N, 2S), the items of
+// the spin-adapted terms (6j weights folded into the coefficients), and the
+// weight itself.
+void su2_layout(const dmrg_basis_s* L, const dmrg_basis_s* R, const int32_t Q[2],
+                std::vector<BlockInfo>* blocks, int64_t* total);
+dmrg_status build_items_su2(struct ::dmrg_heff_s* h, int64_t n_terms, const dmrg_term_su2* terms);
+double su2_weight(int tja, int tjc, int tja2, int tjc2, int tk, int tS);
 // Workspace doubles of one item's intermediate (0 for one-sided items) and
 // its association order (left operator first when cheaper or equal).
 int64_t item_need(const struct ::dmrg_heff_s* h, const Item& it, bool* left_first);
@@ -142,7 +149,8 @@ struct dmrg_heff_s {
   std::vector<int64_t> Ld, Rd;
   int32_t Q[2] = {0, 0};
   std::vector<dmrg::BlockInfo> blocks;
-  std::vector<int32_t> blk_of_left;  // left sector -> block or -1
+  std::vector<int32_t> blk_of_left;  // left sector -> block or -1 (U(1) form)
+  bool su2 = false;                  // spin-adapted form: qn are (N, 2j), Q is (N, 2S)
   int64_t size = 0;
   std::vector<dmrg::Item> items;
   const double* lpool = nullptr;

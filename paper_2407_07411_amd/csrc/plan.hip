@@ -607,13 +607,20 @@ namespace {
 // are pinned host memory and device_bytes bounds the device copies of their
 // blocks (out-of-core form).
 dmrg_status heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
-                        int64_t n_terms, const dmrg_term* terms, const double* left_pool,
-                        int64_t left_pool_len, const double* right_pool, int64_t right_pool_len,
-                        dmrg_prec prec, int64_t device_bytes, dmrg_heff_t* out) {
+                        int64_t n_terms, const dmrg_term* terms, const dmrg_term_su2* sterms,
+                        const double* left_pool, int64_t left_pool_len, const double* right_pool,
+                        int64_t right_pool_len, dmrg_prec prec, int64_t device_bytes, dmrg_heff_t* out) {
   if (!out) return fail(DMRG_EINVAL, "heff_create: out is NULL");
   *out = nullptr;
-  if (!ctx || !L || !R || !Q || n_terms < 0 || (n_terms > 0 && !terms))
+  if (!ctx || !L || !R || !Q || n_terms < 0 || (n_terms > 0 && !terms && !sterms))
     return fail(DMRG_EINVAL, "heff_create: bad arguments");
+  if (sterms) {
+    if (Q[1] < 0) return fail(DMRG_EINVAL, "heff_create_su2: 2S must be >= 0");
+    for (size_t i = 0; i < L->dim.size(); ++i)
+      if (L->qn[2 * i + 1] < 0) return fail(DMRG_EINVAL, "heff_create_su2: left sector with 2j < 0");
+    for (size_t i = 0; i < R->dim.size(); ++i)
+      if (R->qn[2 * i + 1] < 0) return fail(DMRG_EINVAL, "heff_create_su2: right sector with 2j < 0");
+  }
   if (left_pool_len < 0 || right_pool_len < 0 || (left_pool_len > 0 && !left_pool) ||
       (right_pool_len > 0 && !right_pool))
     return fail(DMRG_EINVAL, "heff_create: bad pool");
@@ -634,16 +641,21 @@ dmrg_status heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const in
   h->llen = left_pool_len;
   h->rlen = right_pool_len;
   h->prec = prec;
-  h->blk_of_left.assign(L->dim.size(), -1);
-  int64_t off = 0;
-  for (size_t a = 0; a < L->dim.size(); ++a) {
-    int c = R->find(Q[0] - L->qn[2 * a], Q[1] - L->qn[2 * a + 1]);
-    if (c < 0) continue;
-    h->blk_of_left[a] = (int32_t)h->blocks.size();
-    h->blocks.push_back(BlockInfo{(int32_t)a, c, (int32_t)L->dim[a], (int32_t)R->dim[c], off});
-    off += L->dim[a] * R->dim[c];
+  h->su2 = sterms != nullptr;
+  if (h->su2) {
+    su2_layout(L, R, Q, &h->blocks, &h->size);
+  } else {
+    h->blk_of_left.assign(L->dim.size(), -1);
+    int64_t off = 0;
+    for (size_t a = 0; a < L->dim.size(); ++a) {
+      int c = R->find(Q[0] - L->qn[2 * a], Q[1] - L->qn[2 * a + 1]);
+      if (c < 0) continue;
+      h->blk_of_left[a] = (int32_t)h->blocks.size();
+      h->blocks.push_back(BlockInfo{(int32_t)a, c, (int32_t)L->dim[a], (int32_t)R->dim[c], off});
+      off += L->dim[a] * R->dim[c];
+    }
+    h->size = off;
   }
-  h->size = off;
   if (h->blocks.empty()) return fail(DMRG_EQN, "heff_create: no wavefunction block has total Q");
   if (h->blocks.size() > 65535) return fail(DMRG_ENOTSUP, "heff_create: too many blocks");
   for (const BlockInfo& b : h->blocks)
@@ -654,7 +666,7 @@ dmrg_status heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const in
     dmrg_heff_destroy(h.release());
     return e;
   };
-  dmrg_status st = build_items(h.get(), n_terms, terms);
+  dmrg_status st = h->su2 ? build_items_su2(h.get(), n_terms, sterms) : build_items(h.get(), n_terms, terms);
   if (st != DMRG_OK) return bail(st);
   count_work(h.get());
   h->work_budget = workspace_budget_doubles();
@@ -716,8 +728,17 @@ dmrg_status dmrg_heff_create(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, con
                              int64_t n_terms, const dmrg_term* terms, const double* left_pool,
                              int64_t left_pool_len, const double* right_pool,
                              int64_t right_pool_len, dmrg_prec prec, dmrg_heff_t* out) {
-  return heff_create(ctx, L, R, Q, n_terms, terms, left_pool, left_pool_len, right_pool,
+  return heff_create(ctx, L, R, Q, n_terms, terms, nullptr, left_pool, left_pool_len, right_pool,
                      right_pool_len, prec, -1, out);
+}
+
+dmrg_status dmrg_heff_create_su2(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R, const int32_t Q[2],
+                                 int64_t n_terms, const dmrg_term_su2* terms, const double* left_pool,
+                                 int64_t left_pool_len, const double* right_pool, int64_t right_pool_len,
+                                 dmrg_prec prec, dmrg_heff_t* out) {
+  static const dmrg_term_su2 none{};
+  return heff_create(ctx, L, R, Q, n_terms, nullptr, n_terms > 0 ? terms : &none, left_pool, left_pool_len,
+                     right_pool, right_pool_len, prec, -1, out);
 }
 
 dmrg_status dmrg_heff_create_streamed(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis_t R,
@@ -727,7 +748,7 @@ dmrg_status dmrg_heff_create_streamed(dmrg_ctx_t ctx, dmrg_basis_t L, dmrg_basis
                                       dmrg_prec prec, int64_t device_bytes, dmrg_heff_t* out) {
   if (out) *out = nullptr;
   if (device_bytes < 0) return fail(DMRG_EINVAL, "heff_create_streamed: negative device budget");
-  return heff_create(ctx, L, R, Q, n_terms, terms, left_pool_host, left_pool_len, right_pool_host,
+  return heff_create(ctx, L, R, Q, n_terms, terms, nullptr, left_pool_host, left_pool_len, right_pool_host,
                      right_pool_len, prec, device_bytes, out);
 }
 

@@ -13,10 +13,10 @@ from ctypes import byref, c_double, c_int32, c_int64, c_void_p
 import numpy as np
 import torch
 
-from ._lib import (FP32, FP64, SPLIT_BF16X3, DavOpts, DavResult, DmrgError, Term, check, lib)
+from ._lib import (FP32, FP64, SPLIT_BF16X3, DavOpts, DavResult, DmrgError, Term, TermSU2, check, lib)
 
-__all__ = ["Context", "Heff", "HeffApply", "davidson", "svd_truncate", "FP64", "SPLIT_BF16X3", "FP32",
-           "DmrgError"]
+__all__ = ["Context", "Heff", "HeffSU2", "HeffApply", "davidson", "svd_truncate", "su2_weight",
+           "wfn_layout_su2", "FP64", "SPLIT_BF16X3", "FP32", "DmrgError"]
 
 
 def _ptr(t):
@@ -239,6 +239,66 @@ class Heff:
         check(lib().dmrg_heff_apply_adjoint(self.h, _ptr(psi), _ptr(ybar), _ptr(psibar), _ptr(left_bar),
                                             _ptr(right_bar)))
         return psibar, left_bar, right_bar
+
+
+def su2_weight(two_ja, two_jc, two_ja2, two_jc2, two_k, two_s):
+    """The library's recoupling weight of the SU(2) form (host call)."""
+    return float(lib().dmrg_su2_weight(int(two_ja), int(two_jc), int(two_ja2), int(two_jc2), int(two_k),
+                                       int(two_s)))
+
+
+def wfn_layout_su2(L: Basis, R: Basis, Q):
+    """(left sector, right sector, offset) of every reduced block and the
+    total length of the SU(2) wavefunction."""
+    q = (c_int32 * 2)(int(Q[0]), int(Q[1]))
+    nb, total = c_int64(), c_int64()
+    check(lib().dmrg_wfn_layout_su2(L.h, R.h, q, byref(nb), None, None, None, byref(total)))
+    bl = np.zeros(nb.value, dtype=np.int32)
+    br = np.zeros(nb.value, dtype=np.int32)
+    bo = np.zeros(nb.value, dtype=np.int64)
+    check(lib().dmrg_wfn_layout_su2(L.h, R.h, q, byref(nb), bl.ctypes.data_as(c_void_p),
+                                    br.ctypes.data_as(c_void_p), bo.ctypes.data_as(c_void_p), byref(total)))
+    return bl, br, bo, int(total.value)
+
+
+class HeffSU2(Heff):
+    """H_eff in the SU(2) spin-adapted form: sectors (N, 2j) with multiplet
+    counts, total Q = (N, 2S), terms with a spin rank and reduced blocks
+    listed as (output sector, input sector, offset) rows; the same device
+    pools and calls as Heff."""
+
+    def __init__(self, ctx: Context, Lq, Ld, Rq, Rd, Q, terms, left_pool, right_pool, prec=FP64):
+        self.ctx = ctx
+        self.L = Basis(ctx, Lq, Ld)
+        self.R = Basis(ctx, Rq, Rd)
+        self.left_pool = _dev_f64(left_pool, "left_pool")
+        self.right_pool = _dev_f64(right_pool, "right_pool")
+        arr = (TermSU2 * max(1, len(terms)))()
+        keep = []
+        for i, t in enumerate(terms):
+            x = arr[i]
+            x.two_k, x.dn, x.odd, x.hc = int(t.two_k), int(t.dn), int(t.odd), int(t.hc)
+            x.one_sided, x.reserved, x.coeff = int(t.one_sided), 0, float(t.coeff)
+            for tab, nfld, pfld in ((t.left_blocks, "n_left", "left_blocks"),
+                                    (t.right_blocks, "n_right", "right_blocks")):
+                if tab is None:
+                    setattr(x, nfld, 0)
+                    setattr(x, pfld, ctypes.POINTER(c_int64)())
+                else:
+                    a = np.ascontiguousarray(np.asarray(tab, dtype=np.int64).reshape(-1, 3))
+                    keep.append(a)
+                    setattr(x, nfld, a.shape[0])
+                    setattr(x, pfld, a.ctypes.data_as(ctypes.POINTER(c_int64)))
+        q = (c_int32 * 2)(int(Q[0]), int(Q[1]))
+        self.Q = (int(Q[0]), int(Q[1]))
+        ctx.sync_stream()
+        h = c_void_p()
+        check(lib().dmrg_heff_create_su2(ctx.h, self.L.h, self.R.h, q, len(terms), arr,
+                                         _ptr(self.left_pool), self.left_pool.numel(),
+                                         _ptr(self.right_pool), self.right_pool.numel(), int(prec), byref(h)))
+        self.h = h
+        self._destroy = lib().dmrg_heff_destroy
+        self.size = int(lib().dmrg_heff_size(h))
 
 
 class HeffApply(torch.autograd.Function):

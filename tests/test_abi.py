@@ -22,7 +22,7 @@ def declared_functions():
     for path in glob.glob(os.path.join(ROOT, "include", "*.h")):
         text = open(path).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        for m in re.finditer(r"\b(?:dmrg_status|void|const char\*|int64_t)\s+(dmrg_\w+)\s*\(", text):
+        for m in re.finditer(r"\b(?:dmrg_status|void|const char\*|int64_t|double)\s+(dmrg_\w+)\s*\(", text):
             names.add(m.group(1))
     return names
 
