@@ -339,15 +339,6 @@ def main():
                                          state="FP64 ground state" if ground is not None else "random psi")
             log(f"svd truncation: {svd_s:.3f} s, kept {int(np.sum(kept))}, error {terr:.3e}")
             del U, S, Vt
-    if not args.no_extra:
-        del h  # its workspace; the pools stay for the CPU baseline
-        torch.cuda.empty_cache()
-        extra["out_of_core_" + args.workload] = streamed_timing(dev, w)
-        extra["adjoint_l24_d1024"] = adjoint_timing(dev)
-        # the L=24, D=1024 single FP64 matvec with all 1226 terms, on its own
-        extra["matvec_tflops_l24_d1024_all_terms"] = extra["adjoint_l24_d1024"]["forward_tflops"]
-        extra["sweeps_l8_d64"] = sweep_timing()
-
     cpu = None
     if not args.no_cpu:
         lid = {tuple(q): i for i, q in enumerate(np.asarray(prob.Lq).tolist())}
@@ -356,13 +347,24 @@ def main():
             cpu = cpu_baseline(prob, args.cpu_seconds, lid, rid)
         except Exception as e:  # the GPU result stands without it
             log("cpu baseline failed:", repr(e))
+    pmeta = dict(prob.meta)
+    if not args.no_extra:
+        # the off-path legs need the memory of this workload's plan and pools
+        del h, x, y, prob
+        torch.cuda.empty_cache()
+        extra["out_of_core_" + args.workload] = streamed_timing(dev, w)
+        extra["su2_cas63_58_d4096"] = su2_timing(dev)
+        extra["adjoint_l24_d1024"] = adjoint_timing(dev)
+        # the L=24, D=1024 single FP64 matvec with all 1226 terms, on its own
+        extra["matvec_tflops_l24_d1024_all_terms"] = extra["adjoint_l24_d1024"]["forward_tflops"]
+        extra["sweeps_l8_d64"] = sweep_timing()
     out = dict(metric="H_eff\u00b7\u03c8 TFLOPS/GPU (FP64 vs split-prec) at D=4096; Davidson iter time",
                value=round(value, 3),
                unit="TFLOPS", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(step_ms, 3),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                config=dict(workload=args.workload, L=w["L"], n_elec=w["n_elec"], two_sz=w["two_sz"], D=w["D"],
-                           terms=prob.meta["n_terms"], stored_pairs=prob.meta["n_pairs"],
-                           pool_gb=round(prob.meta["pool_bytes"] / 1e9, 2), psi_len=prob.meta["psi_len"],
+                           terms=pmeta["n_terms"], stored_pairs=pmeta["n_pairs"],
+                           pool_gb=round(pmeta["pool_bytes"] / 1e9, 2), psi_len=pmeta["psi_len"],
                            step="one Davidson iteration incl. one H_eff matvec, hipGraph-captured stages"),
                roofline=roofline, cpu_baseline=cpu, **extra)
     print(json.dumps(out), flush=True)
@@ -481,6 +483,55 @@ def streamed_timing(dev, w, pool_gb=24.0):
                               rel_err_vs_device_pools=err)
             del hs
     log("out-of-core:", out)
+    return out
+
+
+def su2_timing(dev, pool_gb=150.0):
+    """The SU(2) spin-adapted form at the paper's own bond dimension: the
+    CAS(63,58)-shaped doublet bond with D = 4096 multiplets per block,
+    operator pairs capped uniformly to pool_gb; FP64, split and FP32-operand
+    matvecs timed with HIP events, reduced precisions compared with FP64."""
+    import torch
+
+    from paper_2407_07411_amd import heff as H
+    from synth.su2 import WORKLOADS_SU2, make_workload_su2
+    name = "su2_cas63_58_d4096"
+    prob = make_workload_su2(name, device=dev, pool_budget_bytes=int(pool_gb * 1e9))
+    stream = torch.cuda.Stream(dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = dict(D_multiplets=WORKLOADS_SU2[name]["D"], two_s=WORKLOADS_SU2[name]["two_s"],
+               terms=prob.meta["n_terms"], pool_gb=round(prob.meta["pool_bytes"] / 1e9, 2),
+               psi_len=prob.meta["psi_len"], max_sector_multiplets=int(max(prob.Ld.max(), prob.Rd.max())))
+    with torch.cuda.stream(stream):
+        ctx = H.Context(0)
+        t0 = time.time()
+        h = H.HeffSU2(ctx, prob.Lq, prob.Ld, prob.Rq, prob.Rd, prob.Q, prob.terms, prob.left_pool,
+                      prob.right_pool)
+        flops, _ = h.flops()
+        out.update(plan_seconds=round(time.time() - t0, 3), alg_tflop_per_matvec=round(flops / 1e12, 3))
+        x = prob.psi.clone()
+        y64 = torch.empty_like(x)
+        y = torch.empty_like(x)
+        for prec, lab in ((H.FP64, "fp64"), (H.SPLIT_BF16X3, "split"), (H.FP32, "fp32")):
+            h.set_precision(prec)
+            tgt = y64 if lab == "fp64" else y
+            h.apply(x, tgt)
+            ev[0].record(stream)
+            for _ in range(3):
+                h.apply(x, tgt)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / 3
+            out[f"matvec_ms_{lab}"] = round(ms, 3)
+            out[f"matvec_tflops_{lab}"] = round(flops / ms / 1e9, 3)
+            if lab != "fp64":
+                out[f"{lab}_rel_err"] = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
+        h.set_precision(H.FP64)
+    out["split_speedup"] = round(out["matvec_ms_fp64"] / out["matvec_ms_split"], 3)
+    del h, prob
+    torch.cuda.empty_cache()
+    log("su2 cas63_58 D=4096 multiplets:", out)
     return out
 
 

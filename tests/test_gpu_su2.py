@@ -180,3 +180,17 @@ def test_refusals(ctx):
     with pytest.raises(DmrgError) as e:
         plan(ctx, dataclasses.replace(prob, Lq=Lq2))
     assert e.value.status == -1
+
+
+def test_l24_d512_every_term(ctx):
+    """The L=24, 24-electron singlet bond at D=512 multiplets with every
+    operator pair of every class (572 terms, reduced blocks up to 151
+    multiplets, 1.3 GB of pools): the shape class of the U(1) L=24 case."""
+    from synth.su2 import make_workload_su2
+    print("case su2_l24_d512", flush=True)
+    prob = make_workload_su2("su2_l24_d512")
+    h = plan(ctx, prob)
+    y = h.apply(prob.psi.to("cuda")).cpu().numpy()
+    torch.cuda.synchronize()
+    assert rel(y, heff_apply_su2(prob)) <= 1e-12
+    assert h.flops()[0] == count_flops_su2(prob)
