@@ -50,3 +50,37 @@ def test_psi_unit_norm_and_blocks_symmetric():
                     d = int(p.Ld[a])
                     blk = lp[off:off + d * d].reshape(d, d)
                     assert np.array_equal(blk, blk.T)
+
+
+def test_su2_bond_sectors():
+    """Multiplet tables of the SU(2) workloads: electron parity (2j = N mod
+    2); most sectors of each enlarged block pair with one on the other side
+    into the total (N, S) (the rest carry no wavefunction block, as in a
+    real enlarged basis); and the enlarged block holds 4x the states of the
+    block (one site: j x {0, 1/2, 0} with the 1/2 splitting j into j -+ 1/2)."""
+    from synth.su2 import WORKLOADS_SU2, _psi_blocks, bond_sectors_su2
+    for name, w in WORKLOADS_SU2.items():
+        Lq, Ld, Rq, Rd, Q = bond_sectors_su2(w["L"], w["n_elec"], w["two_s"], w["D"])
+        for q in (Lq, Rq):
+            assert all(int(N) % 2 == int(tj) % 2 and tj >= 0 for N, tj in q.tolist())
+        blocks = _psi_blocks(Lq, Rq, Q)
+        assert len({a for a, _ in blocks}) >= 0.75 * len(Lq)
+        assert len({c for _, c in blocks}) >= 0.75 * len(Rq)
+        assert int(Ld.sum()) > w["D"] and int(Rd.sum()) > w["D"]
+        # total states of the enlarged block = 4 x the block's states
+        for q, d in ((Lq, Ld), (Rq, Rd)):
+            states = sum(int(n) * (int(tj) + 1) for (_, tj), n in zip(q.tolist(), d.tolist()))
+            assert states % 4 == 0
+
+
+def test_su2_problem_blocks_obey_selection_rules():
+    from synth.su2 import tiny_su2
+    p = tiny_su2(seed=3, N=6, two_s=2)
+    for t in p.terms:
+        for tab, q, dn in ((t.left_blocks, p.Lq, t.dn), (t.right_blocks, p.Rq, -t.dn)):
+            if tab is None:
+                continue
+            for o, i, _ in np.asarray(tab).tolist():
+                assert int(q[o][0]) - int(q[i][0]) == dn
+                tj, tk, tj2 = int(q[i][1]), t.two_k, int(q[o][1])
+                assert abs(tj - tk) <= tj2 <= tj + tk and (tj + tk + tj2) % 2 == 0
