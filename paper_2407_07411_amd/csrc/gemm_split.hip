@@ -6,12 +6,18 @@
 // f = fp32(a), a0 = bf16(f), a1 = bf16(f - a0), a2 = bf16(f - a0 - a1); the
 // differences are exact in FP32, so a = a0 + a1 + a2 + O(2^-24 |a|).  The
 // product of two split values keeps the six slice products with i + j <= 2
-// (the dropped ones are O(2^-24) relative).  Slice products are exact in FP32;
-// the matrix cores sum them in FP32, and at the end of every segment and every
-// SPLIT_FLUSH_K values of K the FP32 partial, times the segment's alpha, is
-// added into an FP64 accumulator, which bounds FP32 rounding to SPLIT_FLUSH_K K
-// values.  The problem/segment/tile tables and the output-stationary ordering
-// are those of the FP64 kernel, so results are deterministic.
+// (the dropped ones are O(2^-24) relative).  Slice products are exact in FP32
+// and the matrix cores sum them in FP32.  Two accumulation forms: the FP32
+// partial, times the segment's alpha, is added into an FP64 accumulator at
+// the end of every segment and every SPLIT_FLUSH_K values of K (FP32
+// rounding spans at most SPLIT_FLUSH_K values); or, for the 128 x 128 tiles
+// by default, alpha multiplies the operator operand while it is staged, the
+// FP32 accumulators hold the whole sum, and the plan cuts split-precision
+// sums at SPLIT_ACC32_KCHUNK values, whose parts the ordered reduction adds
+// in FP64.  The second form frees the FP64 accumulators' registers, so two
+// workgroups share a CU.  The problem/segment/tile tables and the
+// output-stationary ordering are those of the FP64 kernel, so results are
+// deterministic.
 //
 // Staging: a thread owns groups of 8 K values of one operand row (one row of X
 // or one column of Z).  With KG = BK/8 groups per row and K tile, group kg
@@ -35,6 +41,8 @@
 // Matrix core: v_mfma_f32_32x32x16_bf16.  Lanes: A[i][k] holds i = l%32,
 // k = 8(l/32) + e; B[k][j] holds j = l%32, k = 8(l/32) + e (e = 0..7); the 16
 // result floats of lane l are D[8(v/4) + 4(l/32) + v%4][l%32] (measured).
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace dmrg {
@@ -104,6 +112,24 @@ dmrg_status launch_pack_split(const double* x, double* out, int64_t n, hipStream
 
 constexpr uint32_t OOB_S = 0xffffffffu;
 
+// The 128 x 128 split kernel: the FP32-accumulating one with eight 32 x 64
+// waves in a 61 KB buffer (two workgroups per CU, one staging while the
+// other multiplies) by default; DMRG_HEFF_SPLIT_ACC32 = 0 selects the
+// FP64-accumulating sixteen-wave kernel.  Read once per process.  A/B on the
+// D=4096 matvec (split precision, whole matvec): FP64-accumulating 401 ms,
+// ||dy||/||y|| 2.2e-7; FP32-accumulating with sums cut at 1024 / 2048 / 4096:
+// 370 / 355 / 355 ms, 5.9e-7 / 8.6e-7 / 1.3e-6 (the cut adds ordered FP64
+// reductions); the same with sixteen 32 x 32 waves and 64-deep tiles (one
+// workgroup per CU): 415 ms; eight 64 x 32 waves: as 32 x 64; two 32-deep
+// buffers (one workgroup per CU): 444 ms.
+int split_acc32_variant() {
+  static const int v = [] {
+    const char* e = std::getenv("DMRG_HEFF_SPLIT_ACC32");
+    return e ? std::atoi(e) : 2;
+  }();
+  return v;
+}
+
 // The 8-value groups of one operand (ROWS x BK per K tile) that a thread
 // stages: up to G groups, group r is gi = tid + r * NT < ROWS * KG.
 // Loads go through a buffer resource whose scalar base walks K; per-lane
@@ -169,8 +195,9 @@ struct Stager {
 
   __device__ __forceinline__ void advance() { base += tstep; }
 
-  // Split (or unpack) and store into the three slice planes sh[sl][ROWS][LDK].
-  __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][LDK], int tid) {
+  // Split (or unpack) and store into the three slice planes sh[sl][ROWS][LDK];
+  // an FP64 operand is multiplied by `scale` first (exact when it is 1).
+  __device__ __forceinline__ void store(__bf16 (*sh)[ROWS][LDK], int tid, double scale = 1.0) {
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       if (!EXACT && tid >= NG) continue;
@@ -187,7 +214,8 @@ struct Stager {
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) split_pair(v[r][2 * q], v[r][2 * q + 1], w0[q], w1[q], w2[q]);
+        for (int q = 0; q < 4; ++q)
+          split_pair(scale * v[r][2 * q], scale * v[r][2 * q + 1], w0[q], w1[q], w2[q]);
       }
       const u4v s0 = {w0[0], w0[1], w0[2], w0[3]};
       const u4v s1 = {w1[0], w1[1], w1[2], w1[3]};
@@ -205,10 +233,15 @@ constexpr int split_nbuf() {
 }
 
 // NBUF: LDS buffers (0: two where they fit, else one); BK: K tile depth.
-template <int BM, int BN, int WGM, int WGN, int NBUF = 0, int BK = SPLIT_BK>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
-    Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
-    const Tile* __restrict__ tiles, int64_t ntiles) {
+// ACC64: FP32 partials flushed into FP64 accumulators (every SPLIT_FLUSH_K
+// values and at segment ends, times the segment's alpha); otherwise each
+// segment's alpha multiplies its FP64 operand while it is staged and the
+// FP32 accumulators hold the whole sum (the plan cuts split-precision sums
+// at SPLIT_ACC32_KCHUNK values, so FP32 rounding spans at most that many
+// terms before the parts are added in FP64).
+template <int BM, int BN, int WGM, int WGN, int NBUF = 0, int BK = SPLIT_BK, bool ACC64 = true>
+__device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
+                                           const Tile* __restrict__ tiles, int64_t ntiles) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int NB = NBUF > 0 ? NBUF : split_nbuf<BM, BN, BK>();
   constexpr int LDK = BK + 8;
@@ -236,7 +269,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
   const bool active = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
 
   f16v acc[FM][FN];
-  double acc64[FM][FN][16];
+  double acc64[ACC64 ? FM : 1][ACC64 ? FN : 1][ACC64 ? 16 : 1];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -244,7 +277,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         acc[i][j][v] = 0.f;
-        acc64[i][j][v] = 0.0;
+        if constexpr (ACC64) acc64[i][j][v] = 0.0;
       }
     }
 
@@ -258,8 +291,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
     zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid, (bases.packed >> g.zbuf) & 1u);
     xs.load(g.K);
     zs.load(g.K);
-    xs.store(Xh[0], tid);
-    zs.store(Zh[0], tid);
+    // alpha rides on the operator-pool operand (every split segment has
+    // one; chosen by buffer, so the pre-split and split-while-staging
+    // forms round alike)
+    auto pool_z = [](const Seg& q) { return q.zbuf == BUF_LPOOL || q.zbuf == BUF_RPOOL; };
+    auto pool_x = [](const Seg& q) { return q.xbuf == BUF_LPOOL || q.xbuf == BUF_RPOOL; };
+    double sx = 1.0, sz = 1.0;
+    if constexpr (!ACC64) (pool_z(g) && !pool_x(g) ? sz : sx) = g.alpha;
+    xs.store(Xh[0], tid, sx);
+    zs.store(Zh[0], tid, sz);
     __syncthreads();
     while (true) {
       // next (segment, K tile) position; its global loads go out first
@@ -311,10 +351,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
       }
       if (more) {
         if (NB == 1) __syncthreads();  // every wave is done with the only buffer
-        xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid);
-        zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid);
+        double sx2 = 1.0, sz2 = 1.0;
+        if constexpr (!ACC64) (pool_z(g2) && !pool_x(g2) ? sz2 : sx2) = g2.alpha;
+        xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid, sx2);
+        zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid, sz2);
       }
-      if (++since_flush == FLUSH || seg_end) {
+      if (ACC64 && (++since_flush == FLUSH || seg_end)) {
         since_flush = 0;
         const double al = g.alpha;
 #pragma unroll
@@ -323,7 +365,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
           for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              acc64[i][j][v] += al * (double)acc[i][j][v];
+              if constexpr (ACC64) acc64[i][j][v] += al * (double)acc[i][j][v];
               acc[i][j][v] = 0.f;
             }
       }
@@ -347,7 +389,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
 #pragma unroll
         for (int v = 0; v < 16; v += 2) {
           uint32_t s0, s1, s2;
-          split_pair(acc64[i][j][v], acc64[i][j][v + 1], s0, s1, s2);
+          if constexpr (ACC64)
+            split_pair(acc64[i][j][v], acc64[i][j][v + 1], s0, s1, s2);
+          else
+            split_pair((double)acc[i][j][v], (double)acc[i][j][v + 1], s0, s1, s2);
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int m = m0 + wm * WM + i * 32 + 8 * ((v + h) / 4) + 4 * (lane >> 5) + ((v + h) % 4);
@@ -367,9 +412,29 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
         const int n = n0 + wn * WN + j * 32 + fr;
         if (m < p.M && n < p.N) {
           double* c = C + (int64_t)m * p.ldc + n;
-          *c = p.beta ? *c + acc64[i][j][v] : acc64[i][j][v];
+          double r;
+          if constexpr (ACC64)
+            r = acc64[i][j][v];
+          else
+            r = (double)acc[i][j][v];
+          *c = p.beta ? *c + r : r;
         }
       }
+}
+
+template <int BM, int BN, int WGM, int WGN, int NBUF = 0, int BK = SPLIT_BK>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(
+    Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
+    const Tile* __restrict__ tiles, int64_t ntiles) {
+  split_body<BM, BN, WGM, WGN, NBUF, BK, true>(bases, probs, segs, tiles, ntiles);
+}
+
+// FP32-accumulating variants: 128 x 128 tiles, two workgroups per CU.
+template <int WGM, int WGN, int NBUF, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4))) void gemm_split32_kernel(
+    Bases bases, const Prob* __restrict__ probs, const Seg* __restrict__ segs,
+    const Tile* __restrict__ tiles, int64_t ntiles) {
+  split_body<128, 128, WGM, WGN, NBUF, BK, false>(bases, probs, segs, tiles, ntiles);
 }
 dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                               const Tile* tiles, hipStream_t s) {
@@ -386,8 +451,11 @@ dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs
     case CFG_F64_128:
       gemm_split_kernel<128, 128, 2, 2><<<grid, 256, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
-    case CFG_F64_128W8:  // sixteen 32x32 waves, 64-deep K tiles in one LDS buffer (measured fastest)
-      gemm_split_kernel<128, 128, 4, 4, 1, 64><<<grid, 1024, 0, s>>>(b, probs, segs, t, l.ntiles);
+    case CFG_F64_128W8:
+      if (split_acc32_variant() > 0)  // eight 32x64 waves, 32-deep K tiles in one 61 KB buffer
+        gemm_split32_kernel<4, 2, 1, 32><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);
+      else  // sixteen 32x32 waves, 64-deep K tiles in one LDS buffer, FP64 accumulation
+        gemm_split_kernel<128, 128, 4, 4, 1, 64><<<grid, 1024, 0, s>>>(b, probs, segs, t, l.ntiles);
       break;
     case CFG_F64_64x128:
       gemm_split_kernel<64, 128, 2, 4><<<grid, 512, 0, s>>>(b, probs, segs, t, l.ntiles);

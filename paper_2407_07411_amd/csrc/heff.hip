@@ -285,7 +285,10 @@ int to_dma(int cfg, int M, int N) {
 // launch per configuration.
 void ProgramBuilder::close_phase() {
   // cut long-K problems into parts of about kchunk along segment boundaries
-  const int64_t kchunk = kchunk_from_env();
+  // split precision with FP32-accumulating tiles: sums cut shorter (the
+  // parts are added in FP64 by the ordered reduction)
+  const int64_t kchunk = split && split_acc32_variant() > 0 ? std::min(kchunk_from_env(), SPLIT_ACC32_KCHUNK)
+                                                           : kchunk_from_env();
   const size_t nprob = prog.probs.size();
   const size_t red_first = prog.reds.size();
   int64_t part_used = 0;

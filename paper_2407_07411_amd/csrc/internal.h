@@ -172,6 +172,10 @@ dmrg_status launch_gemm(const Launch& l, const Bases& b, const Prob* probs, cons
 dmrg_status launch_pack_split(const double* x, double* out, int64_t n, hipStream_t s);
 dmrg_status launch_gemm_split(const Launch& l, const Bases& b, const Prob* probs, const Seg* segs,
                               const Tile* tiles, hipStream_t s);
+// Which FP32-accumulating split kernel serves 128 x 128 tiles (0: none, the
+// FP64-accumulating one); its programs cut sums at SPLIT_ACC32_KCHUNK.
+int split_acc32_variant();
+constexpr int64_t SPLIT_ACC32_KCHUNK = 2048;
 dmrg_status launch_reduce(const Launch& l, const Bases& b, const RedBlock* reds,
                           const int64_t* parts, hipStream_t s);
 
