@@ -414,3 +414,113 @@ def expand_to_u1(prob, tM=None):
                   np.concatenate(rpool) if rpool else np.zeros(1),
                   expand_vec(_np(prob.psi)))
     return up, expand_vec
+
+
+# ---------------------------------------------------------------------------
+# Sampled entries of a whole-size problem.
+
+
+@lru_cache(maxsize=None)
+def _weight_cached(tja, tjc, tja2, tjc2, tk, tS):
+    return weight(tja, tjc, tja2, tjc2, tk, tS)
+
+
+def heff_entries_blocks_su2(prob, samples, psi=None):
+    """Entries y[(a', c')][rows, cols] of y = H_eff psi for the sampled output
+    blocks (samples maps (a', c') to (rows, cols)), by the definition of
+    heff_apply_su2 taken item by item, with the sum of the absolute values
+    of the products entering each entry (the scale of its rounding error).
+    Only the items that reach a sampled block are formed, and only the
+    needed rows of their operator blocks leave the pools."""
+    from oracle.heff import _rows_of
+    lay = layout_su2(prob)
+    Lq, Rq = lay.Lq, lay.Rq
+    pools = {"L": prob.left_pool, "R": prob.right_pool}
+    x = _np(prob.psi if psi is None else psi).astype(np.float64)
+    want = set(samples)
+    groups = {}
+    for t in prob.terms:
+        if t.one_sided:
+            stored = t.left_blocks if t.one_sided == 1 else t.right_blocks
+            for (out, inp, off) in np.asarray(stored).tolist():
+                for dst in want:
+                    a2, c2 = dst
+                    if (t.one_sided == 1 and a2 != out) or (t.one_sided == 2 and c2 != out):
+                        continue
+                    src = (inp, c2) if t.one_sided == 1 else (a2, inp)
+                    if src not in lay.offset:
+                        continue
+                    d = int((lay.Ld if t.one_sided == 1 else lay.Rd)[out])
+                    spec = ("L" if t.one_sided == 1 else "R", int(off), d, d)
+                    A, B = (spec, None) if t.one_sided == 1 else (None, spec)
+                    groups.setdefault((src, dst, t.one_sided), []).append((A, False, B, False, t.coeff))
+                # hc: the transposed block carries `out`-side inputs to `inp`-side outputs
+                if t.hc:
+                    for dst in want:
+                        a2, c2 = dst
+                        if (t.one_sided == 1 and a2 != inp) or (t.one_sided == 2 and c2 != inp):
+                            continue
+                        src = (out, c2) if t.one_sided == 1 else (a2, out)
+                        if src not in lay.offset:
+                            continue
+                        d = int((lay.Ld if t.one_sided == 1 else lay.Rd)[out])
+                        spec = ("L" if t.one_sided == 1 else "R", int(off), d, d)
+                        A, B = (spec, None) if t.one_sided == 1 else (None, spec)
+                        groups.setdefault((src, dst, t.one_sided), []).append(
+                            (A, A is not None, B, B is not None, t.coeff))
+            continue
+        # stored blocks indexed by output and by input sector
+        lo_out, lo_in, ro_out, ro_in = {}, {}, {}, {}
+        for (a2, a, lo) in np.asarray(t.left_blocks).tolist():
+            lo_out.setdefault(a2, []).append((a, lo))
+            lo_in.setdefault(a, []).append((a2, lo))
+        for (c2, c, ro) in np.asarray(t.right_blocks).tolist():
+            ro_out.setdefault(c2, []).append((c, ro))
+            ro_in.setdefault(c, []).append((c2, ro))
+
+        def add(a, c, a2, c2, lo, ro, back):
+            # the contribution of input block (a, c) to output (a2, c2); back:
+            # its transpose (input (a2, c2), output (a, c))
+            w = _weight_cached(int(Lq[a][1]), int(Rq[c][1]), int(Lq[a2][1]), int(Rq[c2][1]), t.two_k, lay.tS)
+            if w == 0.0:
+                return
+            s = -1.0 if (t.odd and int(Lq[a][0]) % 2) else 1.0
+            A = ("L", int(lo), int(lay.Ld[a2]), int(lay.Ld[a]))
+            B = ("R", int(ro), int(lay.Rd[c2]), int(lay.Rd[c]))
+            key = ((a2, c2), (a, c), 0) if back else ((a, c), (a2, c2), 0)
+            groups.setdefault(key, []).append((A, back, B, back, t.coeff * s * w))
+
+        for (a2, c2) in want:
+            for (a, lo) in lo_out.get(a2, ()):
+                for (c, ro) in ro_out.get(c2, ()):
+                    if (a, c) in lay.offset:
+                        add(a, c, a2, c2, lo, ro, False)
+            if t.hc:  # (a2, c2) as the input side of an original contribution
+                for (ap, lo) in lo_in.get(a2, ()):
+                    for (cp, ro) in ro_in.get(c2, ()):
+                        if (ap, cp) in lay.offset:
+                            add(a2, c2, ap, cp, lo, ro, True)
+    out = {b: (np.zeros((len(r), len(c))), np.zeros((len(r), len(c)))) for b, (r, c) in samples.items()}
+    for (src, dst, kind), items in groups.items():
+        rows, cols = (list(v) for v in samples[dst])
+        X = lay.block(x, *src)
+        al = np.array([it[4] for it in items])
+        if kind != 2:
+            A_ = _rows_of(pools["L"], [it[0] for it in items], [it[1] for it in items], rows)
+        if kind != 1:
+            B_ = _rows_of(pools["R"], [it[2] for it in items], [it[3] for it in items], cols)
+        if kind == 0:
+            P = (A_.reshape(-1, X.shape[0]) @ X).reshape(len(items), len(rows), -1)
+            Pm = (np.abs(A_).reshape(-1, X.shape[0]) @ np.abs(X)).reshape(len(items), len(rows), -1)
+            v = np.einsum("nrk,nck->nrc", P, B_)
+            m = np.einsum("nrk,nck->nrc", Pm, np.abs(B_))
+        elif kind == 1:
+            v = A_ @ X[:, cols][None, :, :]
+            m = np.abs(A_) @ np.abs(X[:, cols])[None, :, :]
+        else:
+            v = np.einsum("rk,nck->nrc", X[rows, :], B_)
+            m = np.einsum("rk,nck->nrc", np.abs(X[rows, :]), np.abs(B_))
+        val, mag = out[dst]
+        val += np.einsum("n,nrc->rc", al, v)
+        mag += np.einsum("n,nrc->rc", np.abs(al), m)
+    return out

@@ -140,3 +140,20 @@ def test_library_weight_equals_oracle():
         assert abs(su2_weight(tja, tjc, tja2, tjc2, tk, tS) - w) < 1e-13, (tja, tjc, tja2, tjc2, tk, tS)
         n += 1
     assert n > 2000
+
+
+@pytest.mark.parametrize("kw", [CASES[0], CASES[3], dict(seed=11, n_lo=2, n_hi=7, tj_max=5, dmax=12, N=9,
+                                                           two_s=1, pairs=3)])
+def test_sampled_entries_equal_full_matvec(kw):
+    """heff_entries_blocks_su2 (items formed per sampled output block, rows
+    gathered from the pools) reproduces every block of heff_apply_su2."""
+    from oracle.su2 import heff_entries_blocks_su2
+    prob = tiny_su2(**kw)
+    lay = layout_su2(prob)
+    y = heff_apply_su2(prob)
+    samples = {b: (list(range(int(lay.Ld[b[0]]))), list(range(int(lay.Rd[b[1]])))) for b in lay.blocks}
+    got = heff_entries_blocks_su2(prob, samples)
+    for b in lay.blocks:
+        val, mag = got[b]
+        assert np.abs(lay.block(y, *b) - val).max() <= 1e-13 * max(1.0, mag.max())
+        assert np.all(mag >= np.abs(val) - 1e-13)
