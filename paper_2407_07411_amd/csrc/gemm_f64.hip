@@ -92,7 +92,34 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
   if (p.nseg > 0) {
     Stage<BM, BK, NT> xs;
     Stage<BN, BK, NT> zs;
-    int s = p.seg0, k0 = 0;
+    // edge tiles: a wave whose output rows or columns all lie outside the
+    // problem issues no LDS reads or MFMAs
+    auto mma = [&](int b) {
+      if (!active) return;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double a[FM], c[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = Xs[b][kk + fk][wm * WM + i * 16 + fr];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) c[j] = Zs[b][kk + fk][wn * WN + j * 16 + fr];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], c[j], acc[i][j], 0, 0, 0);
+      }
+    };
+    // Loads of the next K tile go out after this tile's MFMAs are issued
+    // (measured faster than before them: the matrix-core work of the other
+    // waves on the SIMD covers their latency); the other LDS buffer was last
+    // read before the previous barrier.  Segments form the outer loop and a
+    // segment's K tiles the inner one, so the staging layout stays fixed
+    // inside the inner loop and only its scalar base moves: written as one
+    // loop over (segment, tile), the compiler carried two copies of the
+    // layout and exchanged them through register moves on every tile, and
+    // each vector instruction takes issue time from the FP64 MFMAs.
+    int s = p.seg0;
     Seg g = segs[s];
     xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
     zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
@@ -103,53 +130,32 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
     __syncthreads();
     int buf = 0;
     while (true) {
-      // next (segment, K tile) position
-      int s2 = s, k2 = k0 + BK;
-      Seg g2 = g;
-      if (k2 >= g.K) {
-        ++s2;
-        k2 = 0;
-        if (s2 < s_end) g2 = segs[s2];
-      }
-      const bool more = s2 < s_end;
-      if (s2 != s) {  // past the last segment g2 == g: harmless, nothing is loaded
-        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
-        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
-      } else {
+      // LDS[buf] holds the first K tile of segment s (a segment with K <= 0
+      // has one tile, of zeros)
+      for (int k0 = BK; k0 < g.K; k0 += BK) {
         xs.advance();
         zs.advance();
+        mma(buf);
+        xs.load(g.K - k0);
+        zs.load(g.K - k0);
+        xs.store(&Xs[buf ^ 1][0][0], g.alpha);
+        zs.store(&Zs[buf ^ 1][0][0], 1.0);
+        __syncthreads();
+        buf ^= 1;
       }
-      // edge tiles: a wave whose output rows or columns all lie outside the
-      // problem issues no LDS reads or MFMAs
-      if (active) {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-          double a[FM], b[FN];
-#pragma unroll
-          for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kk + fk][wm * WM + i * 16 + fr];
-#pragma unroll
-          for (int j = 0; j < FN; ++j) b[j] = Zs[buf][kk + fk][wn * WN + j * 16 + fr];
-#pragma unroll
-          for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-      }
-      if (!more) break;
-      // Loads of the next K tile go out after this tile's MFMAs are issued
-      // (measured faster than before them: the matrix-core work of the other
-      // waves on the SIMD covers their latency).  The other LDS buffer was
-      // last read before the previous barrier.
-      xs.load(g2.K - k2);
-      zs.load(g2.K - k2);
-      xs.store(&Xs[buf ^ 1][0][0], g2.alpha);
+      // LDS[buf] holds the last K tile of segment s; the next segment's
+      // layout is derived after its MFMAs, so that it is not live across them
+      mma(buf);
+      if (++s >= s_end) break;
+      g = segs[s];
+      xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
+      zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+      xs.load(g.K);
+      zs.load(g.K);
+      xs.store(&Xs[buf ^ 1][0][0], g.alpha);
       zs.store(&Zs[buf ^ 1][0][0], 1.0);
       __syncthreads();
       buf ^= 1;
-      s = s2;
-      k0 = k2;
-      g = g2;
     }
   }
 
