@@ -242,7 +242,37 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f32_kernel(
   if (p.nseg > 0) {
     Stage<BM, BK, NT> xs;
     Stage<BN, BK, NT> zs;
-    int s = p.seg0, k0 = 0, since_flush = 0;
+    auto mma = [&](int b) {
+      if (!active) return;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        float a[FM], c[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = Xs[b][kk + fk][wm * WM + i * 16 + fr];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) c[j] = Zs[b][kk + fk][wn * WN + j * 16 + fr];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], c[j], acc[i][j], 0, 0, 0);
+      }
+    };
+    // the FP32 partial sums go into the FP64 ones, times the segment's alpha
+    auto flush = [&](double al) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            acc64[i][j][v] += al * (double)acc[i][j][v];
+            acc[i][j][v] = 0.f;
+          }
+    };
+    // segments as the outer loop and K tiles as the inner one, as in
+    // gemm_f64_kernel
+    int s = p.seg0, since_flush = 0;
     Seg g = segs[s];
     xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
     zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
@@ -253,62 +283,35 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f32_kernel(
     __syncthreads();
     int buf = 0;
     while (true) {
-      int s2 = s, k2 = k0 + BK;
-      Seg g2 = g;
-      if (k2 >= g.K) {
-        ++s2;
-        k2 = 0;
-        if (s2 < s_end) g2 = segs[s2];
-      }
-      const bool more = s2 < s_end;
-      const bool seg_end = s2 != s;
-      if (seg_end) {  // past the last segment g2 == g: harmless, nothing is loaded
-        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
-        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
-      } else {
+      for (int k0 = BK; k0 < g.K; k0 += BK) {
         xs.advance();
         zs.advance();
-      }
-      if (active) {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-          float a[FM], b[FN];
-#pragma unroll
-          for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kk + fk][wm * WM + i * 16 + fr];
-#pragma unroll
-          for (int j = 0; j < FN; ++j) b[j] = Zs[buf][kk + fk][wn * WN + j * 16 + fr];
-#pragma unroll
-          for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-      }
-      if (more) {
-        xs.load(g2.K - k2);
-        zs.load(g2.K - k2);
+        mma(buf);
+        xs.load(g.K - k0);
+        zs.load(g.K - k0);
         xs.store(&Xs[buf ^ 1][0][0], 1.0);
         zs.store(&Zs[buf ^ 1][0][0], 1.0);
+        if (++since_flush == FLUSH) {
+          since_flush = 0;
+          flush(g.alpha);
+        }
+        __syncthreads();
+        buf ^= 1;
       }
-      if (++since_flush == FLUSH || seg_end) {
-        since_flush = 0;
-        const double al = g.alpha;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              acc64[i][j][v] += al * (double)acc[i][j][v];
-              acc[i][j][v] = 0.f;
-            }
-      }
-      if (!more) break;
+      // the last K tile of segment s; its end flushes the partial sums
+      mma(buf);
+      since_flush = 0;
+      flush(g.alpha);
+      if (++s >= s_end) break;
+      g = segs[s];
+      xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
+      zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+      xs.load(g.K);
+      zs.load(g.K);
+      xs.store(&Xs[buf ^ 1][0][0], 1.0);
+      zs.store(&Zs[buf ^ 1][0][0], 1.0);
       __syncthreads();
       buf ^= 1;
-      s = s2;
-      k0 = k2;
-      g = g2;
     }
   }
 
