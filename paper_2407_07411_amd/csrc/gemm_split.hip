@@ -285,45 +285,7 @@ __device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__
   if (p.nseg > 0) {
     Stager<BM, NT, BK> xs;
     Stager<BN, NT, BK> zs;
-    int s = p.seg0, k0 = 0, since_flush = 0, buf = 0;
-    Seg g = segs[s];
-    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid, (bases.packed >> g.xbuf) & 1u);
-    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid, (bases.packed >> g.zbuf) & 1u);
-    xs.load(g.K);
-    zs.load(g.K);
-    // alpha rides on the operator-pool operand (every split segment has
-    // one; chosen by buffer, so the pre-split and split-while-staging
-    // forms round alike)
-    auto pool_z = [](const Seg& q) { return q.zbuf == BUF_LPOOL || q.zbuf == BUF_RPOOL; };
-    auto pool_x = [](const Seg& q) { return q.xbuf == BUF_LPOOL || q.xbuf == BUF_RPOOL; };
-    double sx = 1.0, sz = 1.0;
-    if constexpr (!ACC64) (pool_z(g) && !pool_x(g) ? sz : sx) = g.alpha;
-    xs.store(Xh[0], tid, sx);
-    zs.store(Zh[0], tid, sz);
-    __syncthreads();
-    while (true) {
-      // next (segment, K tile) position; its global loads go out first
-      int s2 = s, k2 = k0 + BK;
-      Seg g2 = g;
-      if (k2 >= g.K) {
-        ++s2;
-        k2 = 0;
-        if (s2 < s_end) g2 = segs[s2];
-      }
-      const bool more = s2 < s_end;
-      const bool seg_end = s2 != s;
-      if (seg_end) {  // past the last segment g2 == g: harmless, nothing is loaded
-        xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid, (bases.packed >> g2.xbuf) & 1u);
-        zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid, (bases.packed >> g2.zbuf) & 1u);
-      } else {
-        xs.advance();
-        zs.advance();
-      }
-      if (more) {
-        xs.load(g2.K - k2);
-        zs.load(g2.K - k2);
-      }
-      const int cb = NB == 2 ? buf : 0;
+    auto mma = [&](int cb) {
 #pragma unroll
       for (int kk = 0; kk < (active ? BK : 0); kk += 16) {
         bf8 a[3][FM], b[3][FN];
@@ -349,31 +311,80 @@ __device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
           }
       }
-      if (more) {
+    };
+    // the FP32 partial sums go into the FP64 ones, times the segment's alpha
+    auto flush = [&](double al) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            if constexpr (ACC64) acc64[i][j][v] += al * (double)acc[i][j][v];
+            acc[i][j][v] = 0.f;
+          }
+    };
+    // alpha rides on the operator-pool operand (every split segment has
+    // one; chosen by buffer, so the pre-split and split-while-staging
+    // forms round alike)
+    auto pool_z = [](const Seg& q) { return q.zbuf == BUF_LPOOL || q.zbuf == BUF_RPOOL; };
+    auto pool_x = [](const Seg& q) { return q.xbuf == BUF_LPOOL || q.xbuf == BUF_RPOOL; };
+    // Segments as the outer loop and K tiles as the inner one (the staging
+    // layout is fixed in the inner loop, as in the FP64 kernel); inside a
+    // segment a tile's global loads go out before the previous tile's MFMAs.
+    int s = p.seg0, since_flush = 0, buf = 0;
+    Seg g = segs[s];
+    xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid, (bases.packed >> g.xbuf) & 1u);
+    zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid, (bases.packed >> g.zbuf) & 1u);
+    xs.load(g.K);
+    zs.load(g.K);
+    double sx = 1.0, sz = 1.0;
+    if constexpr (!ACC64) (pool_z(g) && !pool_x(g) ? sz : sx) = g.alpha;
+    xs.store(Xh[0], tid, sx);
+    zs.store(Zh[0], tid, sz);
+    __syncthreads();
+    while (true) {
+      for (int k0 = BK; k0 < g.K; k0 += BK) {
+        xs.advance();
+        zs.advance();
+        xs.load(g.K - k0);
+        zs.load(g.K - k0);
+        mma(NB == 2 ? buf : 0);
         if (NB == 1) __syncthreads();  // every wave is done with the only buffer
-        double sx2 = 1.0, sz2 = 1.0;
-        if constexpr (!ACC64) (pool_z(g2) && !pool_x(g2) ? sz2 : sx2) = g2.alpha;
-        xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid, sx2);
-        zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid, sz2);
+        xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid, sx);
+        zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid, sz);
+        if (ACC64 && ++since_flush == FLUSH) {
+          since_flush = 0;
+          flush(g.alpha);
+        }
+        __syncthreads();
+        buf ^= 1;
       }
-      if (ACC64 && (++since_flush == FLUSH || seg_end)) {
+      // the last K tile of segment s; its end flushes the partial sums.  The
+      // next segment's layout is derived and its first tile loaded after
+      // these MFMAs, so that the layout is not live across them.
+      mma(NB == 2 ? buf : 0);
+      if (++s >= s_end) {
+        if constexpr (ACC64) flush(g.alpha);
+        break;
+      }
+      const Seg g2 = segs[s];
+      xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid, (bases.packed >> g2.xbuf) & 1u);
+      zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid, (bases.packed >> g2.zbuf) & 1u);
+      xs.load(g2.K);
+      zs.load(g2.K);
+      if (NB == 1) __syncthreads();
+      sx = 1.0;
+      sz = 1.0;
+      if constexpr (!ACC64) (pool_z(g2) && !pool_x(g2) ? sz : sx) = g2.alpha;
+      xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid, sx);
+      zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid, sz);
+      if constexpr (ACC64) {
         since_flush = 0;
-        const double al = g.alpha;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              if constexpr (ACC64) acc64[i][j][v] += al * (double)acc[i][j][v];
-              acc[i][j][v] = 0.f;
-            }
+        flush(g.alpha);
       }
-      if (!more) break;
       __syncthreads();
       buf ^= 1;
-      s = s2;
-      k0 = k2;
       g = g2;
     }
   }
