@@ -238,7 +238,25 @@ __global__ __launch_bounds__(P_NT) __attribute__((amdgpu_waves_per_eu(6))) void 
       }
       Stage<BM, BK, NT> xs;
       Stage<BN, BK, NT> zs;
-      int s = p.seg0, k0 = 0;
+      auto mma = [&](int b) {
+        if (!act) return;
+        const double* X = Xb + b * BK * XLD;
+        const double* Z = Zb + b * BK * ZLD;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          double a[FM], c[FN];
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a[i] = X[(kk + fk) * XLD + wm * WM + i * 16 + fr];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) c[j] = Z[(kk + fk) * ZLD + wn * WN + j * 16 + fr];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], c[j], acc[i][j], 0, 0, 0);
+        }
+      };
+      int s = p.seg0;
       Seg g = segs[s];
       xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
       zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
@@ -252,89 +270,67 @@ __global__ __launch_bounds__(P_NT) __attribute__((amdgpu_waves_per_eu(6))) void 
       int nxph = sh_phase[0];
       int nd = 1;  // dequeues of this chain (slot of the next one: nd & 1)
       int buf = 0;
+      // Segments as the outer loop and K tiles as the inner one, as in the
+      // per-phase kernel; past the end of this tile's sum the chain moves on
+      // to the next task when that is a GEMM tile of this phase and shape with
+      // something to sum.
       while (true) {
-        // next (segment, K tile) position; past the end of this tile's sum
-        // it moves on to the next task when that is a GEMM tile of this phase
-        // and shape with something to sum
-        int s2 = s, k2 = k0 + BK;
-        Seg g2 = g;
-        bool cross = false, more = true;
-        int32_t nprob = -1;
-        int nm0 = 0, nn0 = 0;
-        if (k2 >= g.K) {
-          ++s2;
-          k2 = 0;
-          if (s2 < p.seg0 + p.nseg) {
-            g2 = segs[s2];
-          } else {
-            more = false;
-            if (nxt >= 0 && nxph == ph) {
-              const PTask U = tasks[nxt];
-              if (U.prob >= 0 && (U.tn >> 14) == mode && probs[U.prob].nseg > 0) {
-                cross = more = true;
-                nprob = U.prob;
-                nm0 = U.tm * BM;
-                nn0 = (U.tn & 0x3fff) * BN;
-                s2 = probs[nprob].seg0;
-                g2 = segs[s2];
-              }
-            }
-          }
-        }
-        if (cross) {
-          const Prob q = probs[nprob];
-          xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, nm0, q.M, tid);
-          zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, nn0, q.N, tid);
-        } else if (s2 != s && more) {
-          xs.setup(bases.p[g2.xbuf] + g2.xoff, g2.ldx, !g2.xt, m0, p.M, tid);
-          zs.setup(bases.p[g2.zbuf] + g2.zoff, g2.ldz, g2.zt, n0, p.N, tid);
-        } else if (more) {
+        for (int k0 = BK; k0 < g.K; k0 += BK) {
           xs.advance();
           zs.advance();
+          mma(buf);
+          xs.load(g.K - k0);
+          zs.load(g.K - k0);
+          xs.store(Xb + (buf ^ 1) * BK * XLD, g.alpha);
+          zs.store(Zb + (buf ^ 1) * BK * ZLD, 1.0);
+          __syncthreads();
+          buf ^= 1;
         }
-        if (act) {
-          const double* X = Xb + buf * BK * XLD;
-          const double* Z = Zb + buf * BK * ZLD;
-#pragma unroll
-          for (int kk = 0; kk < BK; kk += 4) {
-            double a[FM], b[FN];
-#pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = X[(kk + fk) * XLD + wm * WM + i * 16 + fr];
-#pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = Z[(kk + fk) * ZLD + wn * WN + j * 16 + fr];
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-              for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-          }
+        // the last K tile of segment s
+        mma(buf);
+        if (++s < p.seg0 + p.nseg) {
+          g = segs[s];
+          xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
+          zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, n0, p.N, tid);
+          xs.load(g.K);
+          zs.load(g.K);
+          xs.store(Xb + (buf ^ 1) * BK * XLD, g.alpha);
+          zs.store(Zb + (buf ^ 1) * BK * ZLD, 1.0);
+          __syncthreads();
+          buf ^= 1;
+          continue;
         }
-        if (!more) break;
-        xs.load(g2.K - k2);
-        zs.load(g2.K - k2);
-        if (cross && tid == 0) dequeue(ph, nd & 1);  // the task after the next, read after the barrier
-        xs.store(Xb + (buf ^ 1) * BK * XLD, g2.alpha);
+        int32_t nprob = -1;
+        if (nxt >= 0 && nxph == ph) {
+          const PTask U = tasks[nxt];
+          if (U.prob >= 0 && (U.tn >> 14) == mode && probs[U.prob].nseg > 0) nprob = U.prob;
+        }
+        if (nprob < 0) break;
+        const PTask U = tasks[nxt];
+        const Prob q = probs[nprob];
+        const int nm0 = U.tm * BM, nn0 = (U.tn & 0x3fff) * BN;
+        s = q.seg0;
+        g = segs[s];
+        xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, nm0, q.M, tid);
+        zs.setup(bases.p[g.zbuf] + g.zoff, g.ldz, g.zt, nn0, q.N, tid);
+        xs.load(g.K);
+        zs.load(g.K);
+        if (tid == 0) dequeue(ph, nd & 1);  // the task after the next, read after the barrier
+        xs.store(Xb + (buf ^ 1) * BK * XLD, g.alpha);
         zs.store(Zb + (buf ^ 1) * BK * ZLD, 1.0);
-        if (cross) {
-          // this tile's sum is complete: store it, start the next one
-          store_acc();
-          ++mine;
-          p = probs[nprob];
-          m0 = nm0;
-          n0 = nn0;
-          act = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
-          init_acc();
-        }
+        // this tile's sum is complete: store it, start the next one
+        store_acc();
+        ++mine;
+        p = q;
+        m0 = nm0;
+        n0 = nn0;
+        act = m0 + wm * WM < p.M && n0 + wn * WN < p.N;
+        init_acc();
         __syncthreads();
-        if (cross) {
-          nxt = sh_task[nd & 1];
-          nxph = sh_phase[nd & 1];
-          ++nd;
-        }
+        nxt = sh_task[nd & 1];
+        nxph = sh_phase[nd & 1];
+        ++nd;
         buf ^= 1;
-        s = s2;
-        k0 = k2;
-        g = g2;
       }
       store_acc();
       ++mine;
