@@ -94,10 +94,13 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
     Stage<BN, BK, NT> zs;
     // edge tiles: a wave whose output rows or columns all lie outside the
     // problem issues no LDS reads or MFMAs
-    auto mma = [&](int b) {
+    // nk: the K steps of 4 that hold data; a segment's last K tile skips the
+    // rest (zero padding), the inner loop's full tiles take them all
+    auto mma = [&](int b, int nk) {
       if (!active) return;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
+        if (kk >= 4 * nk) break;
         double a[FM], c[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i) a[i] = Xs[b][kk + fk][wm * WM + i * 16 + fr];
@@ -135,7 +138,7 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
       for (int k0 = BK; k0 < g.K; k0 += BK) {
         xs.advance();
         zs.advance();
-        mma(buf);
+        mma(buf, BK / 4);
         xs.load(g.K - k0);
         zs.load(g.K - k0);
         xs.store(&Xs[buf ^ 1][0][0], g.alpha);
@@ -145,7 +148,7 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
       }
       // LDS[buf] holds the last K tile of segment s; the next segment's
       // layout is derived after its MFMAs, so that it is not live across them
-      mma(buf);
+      mma(buf, g.K > 0 ? (g.K - 1) % BK / 4 + 1 : 0);
       if (++s >= s_end) break;
       g = segs[s];
       xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
@@ -242,10 +245,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f32_kernel(
   if (p.nseg > 0) {
     Stage<BM, BK, NT> xs;
     Stage<BN, BK, NT> zs;
-    auto mma = [&](int b) {
+    // nk: the K steps of 4 that hold data (as in gemm_f64_kernel)
+    auto mma = [&](int b, int nk) {
       if (!active) return;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
+        if (kk >= 4 * nk) break;
         float a[FM], c[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i) a[i] = Xs[b][kk + fk][wm * WM + i * 16 + fr];
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f32_kernel(
       for (int k0 = BK; k0 < g.K; k0 += BK) {
         xs.advance();
         zs.advance();
-        mma(buf);
+        mma(buf, BK / 4);
         xs.load(g.K - k0);
         zs.load(g.K - k0);
         xs.store(&Xs[buf ^ 1][0][0], 1.0);
@@ -299,7 +304,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f32_kernel(
         buf ^= 1;
       }
       // the last K tile of segment s; its end flushes the partial sums
-      mma(buf);
+      mma(buf, g.K > 0 ? (g.K - 1) % BK / 4 + 1 : 0);
       since_flush = 0;
       flush(g.alpha);
       if (++s >= s_end) break;

@@ -238,12 +238,15 @@ __global__ __launch_bounds__(P_NT) __attribute__((amdgpu_waves_per_eu(6))) void 
       }
       Stage<BM, BK, NT> xs;
       Stage<BN, BK, NT> zs;
-      auto mma = [&](int b) {
+      // nk: the K steps of 4 that hold data (a segment's last K tile skips
+      // its zero padding, as in the per-phase kernel)
+      auto mma = [&](int b, int nk) {
         if (!act) return;
         const double* X = Xb + b * BK * XLD;
         const double* Z = Zb + b * BK * ZLD;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
+          if (kk >= 4 * nk) break;
           double a[FM], c[FN];
 #pragma unroll
           for (int i = 0; i < FM; ++i) a[i] = X[(kk + fk) * XLD + wm * WM + i * 16 + fr];
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(P_NT) __attribute__((amdgpu_waves_per_eu(6))) void 
         for (int k0 = BK; k0 < g.K; k0 += BK) {
           xs.advance();
           zs.advance();
-          mma(buf);
+          mma(buf, BK / 4);
           xs.load(g.K - k0);
           zs.load(g.K - k0);
           xs.store(Xb + (buf ^ 1) * BK * XLD, g.alpha);
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(P_NT) __attribute__((amdgpu_waves_per_eu(6))) void 
           buf ^= 1;
         }
         // the last K tile of segment s
-        mma(buf);
+        mma(buf, g.K > 0 ? (g.K - 1) % BK / 4 + 1 : 0);
         if (++s < p.seg0 + p.nseg) {
           g = segs[s];
           xs.setup(bases.p[g.xbuf] + g.xoff, g.ldx, !g.xt, m0, p.M, tid);
