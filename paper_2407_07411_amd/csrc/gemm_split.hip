@@ -285,6 +285,9 @@ __device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__
   if (p.nseg > 0) {
     Stager<BM, NT, BK> xs;
     Stager<BN, NT, BK> zs;
+    // The slice planes hold a K tile in permuted order (value e of group kg
+    // is k = kg + KG * e), so unlike the FP64 kernel a segment's last tile
+    // runs its full depth: its zero padding is spread over both K steps.
     auto mma = [&](int cb) {
 #pragma unroll
       for (int kk = 0; kk < (active ? BK : 0); kk += 16) {
