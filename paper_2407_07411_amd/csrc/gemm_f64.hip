@@ -134,7 +134,7 @@ __attribute__((amdgpu_waves_per_eu(BM == 64 && BN == 128 ? 6 : 1))) void gemm_f6
     int buf = 0;
     while (true) {
       // LDS[buf] holds the first K tile of segment s (a segment with K <= 0
-      // has one tile, of zeros)
+      // stages one tile of zeros and issues no MFMAs)
       for (int k0 = BK; k0 < g.K; k0 += BK) {
         xs.advance();
         zs.advance();
