@@ -278,14 +278,15 @@ dmrg_status dmrg_heff_check(dmrg_heff_t h);
  * own problems, grouped by phase (intermediates / output sums) and by the
  * (M, N) size class (<=16, 32, 64, 128, 256, 512, larger), keeps the fastest
  * shape per group and rebuilds the plan with it, keeping the rebuilt plan
- * only when its whole matvec beats the previous plan's (a phase runs its
- * shapes side by side, which per-group timing does not see).  The timing runs the
+ * only when its whole matvec beats the previous plan's by more than 2% (a
+ * phase runs its shapes side by side, which per-group timing does not see;
+ * smaller differences are timing noise).  The timing runs the
  * current precision's kernels on the context stream with psi and y (device
  * double[size]; y and the workspace are overwritten).  reps >= 1 timed
  * launches per candidate.  The adjoint keeps the built-in rule.  For FP64
  * it then times the kept matvec as per-phase launches and as the single
- * persistent launch (dmrg_heff_set_persistent) and keeps the faster form.
- * Synchronises. */
+ * persistent launch (dmrg_heff_set_persistent) and keeps the persistent
+ * form only when it is faster by more than the same margin.  Synchronises. */
 dmrg_status dmrg_heff_autotune(dmrg_heff_t h, const double* psi, double* y, int32_t reps);
 
 /* Profiling: the matvec is a fixed sequence of grouped-GEMM launches.
