@@ -110,7 +110,6 @@ dmrg_status launch_pack_split(const double* x, double* out, int64_t n, hipStream
   return DMRG_OK;
 }
 
-constexpr uint32_t OOB_S = 0xffffffffu;
 
 // The 128 x 128 split kernel: the FP32-accumulating one with eight 32 x 64
 // waves in a 61 KB buffer (two workgroups per CU, one staging while the
@@ -131,44 +130,73 @@ int split_acc32_variant() {
 }
 
 // The 8-value groups of one operand (ROWS x BK per K tile) that a thread
-// stages: up to G groups, group r is gi = tid + r * NT < ROWS * KG.
-// Loads go through a buffer resource whose scalar base walks K; per-lane
-// offsets are fixed for a segment and the step between the 8 values of a group
-// is a scalar offset, so full K tiles cost no vector address arithmetic.  Rows
-// outside the problem are clamped to its last row: they feed only outputs
-// that are never stored.  In the K tail, offsets at or beyond num_records
-// read as zero (with no scalar offset added).
+// stages: up to G groups, group r is gi = tid + r * NT < ROWS * KG.  The
+// slice planes hold the tile in natural K order, and the assignment follows
+// the operand's layout so that every load instruction is coalesced:
+// * contiguous in the row index (element (row, k) at base + k*ld + row): a
+//   group is one row at 8 consecutive k, consecutive lanes take consecutive
+//   rows; each value is one 8-byte load, the group's slices one 16-byte LDS
+//   store each;
+// * contiguous in K (base + row*ld + k): a group is one K pair (2 consecutive
+//   k) in 4 rows ROWS/4 apart, consecutive lanes take consecutive pairs of a
+//   row (16 lanes read a 256-byte row of a 32-deep tile); each pair is one
+//   16-byte load and its slices 4-byte LDS stores.  (Eight consecutive k per
+//   lane instead would touch four times as many cache lines per load.)
+// Loads go through a buffer resource whose scalar base walks K, per-lane
+// offsets fixed for a segment, so full K tiles cost no vector address
+// arithmetic.  Rows outside the problem are clamped to its last row: they
+// feed only outputs that are never stored.  In the K tail, offsets at or
+// beyond num_records read as zero, and a pair whose second value lies past
+// K loads its first value alone.
 template <int ROWS, int NT, int BK>
 struct Stager {
   static constexpr int KG = BK / 8;       // 8-value groups per row and K tile
+  static constexpr int PPR = BK / 2;      // K pairs per row
   static constexpr int LDK = BK + 8;      // LDS row length (bf16)
   static constexpr int NG = ROWS * KG;
   static constexpr int G = (NG + NT - 1) / NT;
   static constexpr bool EXACT = NG % NT == 0;
   static_assert(EXACT || G == 1, "staging shape");
+  static_assert(ROWS % 4 == 0 && BK % 8 == 0, "staging shape");
+  // An offset past the 2^31 - 1 byte range of every operand, also with any
+  // of the scalar offsets added (they stay below 2^31, so the sum does not
+  // wrap): its reads return zeros.
+  static constexpr uint32_t OOB_K = 0x80000000u;
   const double* base;  // uniform: the block's first row at the current k0
   bool pk;             // uniform: the operand holds packed words
+  bool kc;             // uniform: the operand is contiguous in K
   int64_t tstep;       // uniform: elements between K tiles
-  uint32_t estep;      // uniform: bytes between value e and e + 1 of a group
-  uint32_t off[G];     // byte offset of value 0 of each group (OOB outside the problem)
-  int row[G], kg[G];
+  uint32_t estep;      // uniform: row-contiguous, bytes between value e and e + 1;
+                       // K-contiguous, bytes between pair q and q + 1 (ROWS / 4 rows)
+  uint32_t off[G];     // byte offset of value 0 (row-contiguous) or pair 0
+  int lds[G];          // LDS index of value 0 or pair 0 in a slice plane
+  int nv[G];           // K-contiguous: pairs in rows inside the problem (0..4)
+
   double v[G][8];
 
-  // kc: the operand is contiguous in K (element (row, k) at base + row*ld + k);
-  // otherwise it is contiguous in the row index (base + k*ld + row).
-  __device__ __forceinline__ void setup(const double* seg, int ld, bool kc, int r0, int nrows,
+  __device__ __forceinline__ void setup(const double* seg, int ld, bool kc_, int r0, int nrows,
                                         int tid, bool packed) {
     pk = packed;
+    kc = kc_;
     base = kc ? seg + (int64_t)r0 * ld : seg + r0;
     tstep = kc ? (int64_t)BK : (int64_t)BK * ld;
-    estep = kc ? 8u * KG : 8u * KG * (uint32_t)ld;
+    estep = kc ? 8u * (uint32_t)(ROWS / 4) * (uint32_t)ld : 8u * (uint32_t)ld;
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const int gi = EXACT ? tid + r * NT : min(tid, NG - 1);
-      row[r] = kc ? gi / KG : gi % ROWS;
-      kg[r] = kc ? gi % KG : gi / ROWS;
-      const int rc = min(row[r], nrows - 1 - r0);
-      off[r] = kc ? (uint32_t)(rc * ld + kg[r]) * 8u : (uint32_t)(kg[r] * ld + rc) * 8u;
+      if (kc) {
+        const int kp = gi % PPR, row = gi / PPR;
+        const int inside = nrows - r0 - row;  // rows row + q * ROWS / 4 < nrows - r0
+        nv[r] = inside <= 0 ? 0 : min(4, (inside + ROWS / 4 - 1) / (ROWS / 4));
+        off[r] = (uint32_t)(row * ld + 2 * kp) * 8u;
+        lds[r] = row * LDK + 2 * kp;
+      } else {
+        const int row = gi % ROWS, kg = gi / ROWS;
+        const int rc = min(row, nrows - 1 - r0);
+        nv[r] = 4;
+        off[r] = (uint32_t)(8 * kg * ld + rc) * 8u;
+        lds[r] = row * LDK + 8 * kg;
+      }
     }
   }
 
@@ -176,7 +204,32 @@ struct Stager {
   __device__ __forceinline__ void load(int kleft) {
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, 0x7fffffff, 0x00020000);
-    if (kleft >= BK) {
+    auto pair = [&](int r, int q, uint32_t o) {
+      const u4v w = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(rs, o, q * estep, 0));
+      v[r][2 * q] = __builtin_bit_cast(double, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
+      v[r][2 * q + 1] = __builtin_bit_cast(double, (uint64_t)w[2] | ((uint64_t)w[3] << 32));
+    };
+    if (kc && kleft >= BK) {
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pair(r, q, q < nv[r] ? off[r] : OOB_K);
+    } else if (kc) {
+      // the K tail: each value of a pair loaded on its own, masked by lane
+      // (no branch on the lane's K column, which would split the wave)
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int k = lds[r] % LDK;  // the pair's first K column
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool in = q < nv[r];
+          v[r][2 * q] = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rs, in && k < kleft ? off[r] : OOB_K, q * estep, 0));
+          v[r][2 * q + 1] = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rs, in && k + 1 < kleft ? off[r] : OOB_K, q * estep + 8, 0));
+        }
+      }
+    } else if (kleft >= BK) {
 #pragma unroll
       for (int r = 0; r < G; ++r)
 #pragma unroll
@@ -184,16 +237,32 @@ struct Stager {
           v[r][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off[r], e * estep, 0));
     } else {
 #pragma unroll
-      for (int r = 0; r < G; ++r)
+      for (int r = 0; r < G; ++r) {
+        const int k0 = lds[r] % LDK;  // the group's first K column
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t o = kg[r] + KG * e < kleft ? off[r] + e * estep : OOB_S;
-          v[r][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, o, 0, 0));
-        }
+        for (int e = 0; e < 8; ++e)
+          v[r][e] = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rs, k0 + e < kleft ? off[r] : OOB_K, e * estep, 0));
+      }
     }
   }
 
   __device__ __forceinline__ void advance() { base += tstep; }
+
+  // The three slice words (values a, b as the low and high halves) of a pair.
+  __device__ __forceinline__ void slices(double a, double b, double scale, uint32_t& w0, uint32_t& w1,
+                                         uint32_t& w2) const {
+    if (pk) {
+      const uint64_t u = __builtin_bit_cast(uint64_t, a);
+      const uint64_t w = __builtin_bit_cast(uint64_t, b);
+      const uint32_t ulo = (uint32_t)u, wlo = (uint32_t)w;
+      w0 = (ulo & 0xffffu) | (wlo << 16);
+      w1 = (ulo >> 16) | (wlo & 0xffff0000u);
+      w2 = (uint32_t)(u >> 32) | ((uint32_t)(w >> 32) << 16);
+    } else {
+      split_pair(scale * a, scale * b, w0, w1, w2);
+    }
+  }
 
   // Split (or unpack) and store into the three slice planes sh[sl][ROWS][LDK];
   // an FP64 operand is multiplied by `scale` first (exact when it is 1).
@@ -201,28 +270,28 @@ struct Stager {
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       if (!EXACT && tid >= NG) continue;
-      uint32_t w0[4], w1[4], w2[4];
-      if (pk) {
+      __bf16* p0 = &sh[0][0][0] + lds[r];
+      if (kc) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const uint64_t u = __builtin_bit_cast(uint64_t, v[r][2 * q]);
-          const uint64_t w = __builtin_bit_cast(uint64_t, v[r][2 * q + 1]);
-          const uint32_t ulo = (uint32_t)u, wlo = (uint32_t)w;
-          w0[q] = (ulo & 0xffffu) | (wlo << 16);
-          w1[q] = (ulo >> 16) | (wlo & 0xffff0000u);
-          w2[q] = (uint32_t)(u >> 32) | ((uint32_t)(w >> 32) << 16);
+          uint32_t w0, w1, w2;
+          slices(v[r][2 * q], v[r][2 * q + 1], scale, w0, w1, w2);
+          __bf16* p = p0 + q * (ROWS / 4) * LDK;
+          *reinterpret_cast<uint32_t*>(p) = w0;
+          *reinterpret_cast<uint32_t*>(p + ROWS * LDK) = w1;
+          *reinterpret_cast<uint32_t*>(p + 2 * ROWS * LDK) = w2;
         }
       } else {
+        uint32_t w0[4], w1[4], w2[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          split_pair(scale * v[r][2 * q], scale * v[r][2 * q + 1], w0[q], w1[q], w2[q]);
+        for (int q = 0; q < 4; ++q) slices(v[r][2 * q], v[r][2 * q + 1], scale, w0[q], w1[q], w2[q]);
+        const u4v s0 = {w0[0], w0[1], w0[2], w0[3]};
+        const u4v s1 = {w1[0], w1[1], w1[2], w1[3]};
+        const u4v s2 = {w2[0], w2[1], w2[2], w2[3]};
+        *reinterpret_cast<u4v*>(p0) = s0;
+        *reinterpret_cast<u4v*>(p0 + ROWS * LDK) = s1;
+        *reinterpret_cast<u4v*>(p0 + 2 * ROWS * LDK) = s2;
       }
-      const u4v s0 = {w0[0], w0[1], w0[2], w0[3]};
-      const u4v s1 = {w1[0], w1[1], w1[2], w1[3]};
-      const u4v s2 = {w2[0], w2[1], w2[2], w2[3]};
-      *reinterpret_cast<u4v*>(&sh[0][row[r]][8 * kg[r]]) = s0;
-      *reinterpret_cast<u4v*>(&sh[1][row[r]][8 * kg[r]]) = s1;
-      *reinterpret_cast<u4v*>(&sh[2][row[r]][8 * kg[r]]) = s2;
     }
   }
 };
@@ -285,12 +354,12 @@ __device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__
   if (p.nseg > 0) {
     Stager<BM, NT, BK> xs;
     Stager<BN, NT, BK> zs;
-    // The slice planes hold a K tile in permuted order (value e of group kg
-    // is k = kg + KG * e), so unlike the FP64 kernel a segment's last tile
-    // runs its full depth: its zero padding is spread over both K steps.
-    auto mma = [&](int cb) {
+    // nk: the K steps of 16 that hold data (the slice planes hold the tile
+    // in natural K order, so a segment's last tile skips its zero padding)
+    auto mma = [&](int cb, int nk) {
 #pragma unroll
       for (int kk = 0; kk < (active ? BK : 0); kk += 16) {
+        if (kk >= 16 * nk) break;
         bf8 a[3][FM], b[3][FN];
 #pragma unroll
         for (int sl = 0; sl < 3; ++sl) {
@@ -352,7 +421,7 @@ __device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__
         zs.advance();
         xs.load(g.K - k0);
         zs.load(g.K - k0);
-        mma(NB == 2 ? buf : 0);
+        mma(NB == 2 ? buf : 0, BK / 16);
         if (NB == 1) __syncthreads();  // every wave is done with the only buffer
         xs.store(Xh[NB == 2 ? buf ^ 1 : 0], tid, sx);
         zs.store(Zh[NB == 2 ? buf ^ 1 : 0], tid, sz);
@@ -366,7 +435,7 @@ __device__ __forceinline__ void split_body(Bases bases, const Prob* __restrict__
       // the last K tile of segment s; its end flushes the partial sums.  The
       // next segment's layout is derived and its first tile loaded after
       // these MFMAs, so that the layout is not live across them.
-      mma(NB == 2 ? buf : 0);
+      mma(NB == 2 ? buf : 0, g.K > 0 ? (g.K - 1) % BK / 16 + 1 : 0);
       if (++s >= s_end) {
         if constexpr (ACC64) flush(g.alpha);
         break;
