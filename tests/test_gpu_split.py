@@ -6,12 +6,15 @@ to FP32, 2^-24 relative, like the slices), under the same bound.
 Stated bound for the matvec: ||y_split - y||_2 <= 1e-5 ||y||_2.  Derivation:
 the slices represent each operand to ~2^-24 relative (FP32 rounding of the
 FP64 value plus the slicing), the six kept slice products drop terms of
-~2^-24 relative, and each FP32 partial sums at most 4 x 32 K values x 6
-products before it is added into FP64: with independent rounding errors the
-relative error of an output is ~sqrt(768) x 2^-24 ~ 2e-6 (the worst case,
-all errors aligned, is 768 x 2^-24 ~ 5e-5); the parity runs see ~2e-7.  Energies: the split phase stalls near the matvec error
-and an FP64 tail restarted from its Ritz vector converges to the FP64
-tolerance, so the energy must match the FP64 solve to 1e-8."""
+~2^-24 relative, and an FP32 partial sums at most 2048 K values x 6 products
+(the plan cuts split-precision sums every 2048 K values; the
+FP64-accumulating kernels flush every 128) before it is added into FP64:
+with independent rounding errors the relative error of an output is
+~sqrt(12288) x 2^-24 ~ 7e-6, and below 1e-6 where, as here, the terms of a
+sum vary in sign and size (aligned worst case: 12288 x 2^-24 ~ 7e-4); the
+parity runs see 2e-7 to 9e-7.  Energies: the split phase stalls near the
+matvec error and an FP64 tail restarted from its Ritz vector converges to
+the FP64 tolerance, so the energy must match the FP64 solve to 1e-8."""
 import numpy as np
 import pytest
 import torch
@@ -97,3 +100,34 @@ def test_presplit_operands_bit_identical(ctx, kind, tile, monkeypatch):
             h0.apply(psi * 0.5)  # other work between the replays
             torch.cuda.synchronize()
         h1.use_graph(False)
+
+
+def test_fp64_accumulating_128_kernel_in_a_child_process():
+    """The FP64-accumulating 128x128 split kernel (sixteen 32x32 waves,
+    selected by DMRG_HEFF_SPLIT_ACC32=0, which the library reads once per
+    process) on the L=24 problem with every product forced onto the
+    128x128 shape, in a child process, under the stated bound."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import json, torch\n"
+        "from oracle.heff import heff_apply\n"
+        "from tests.test_gpu_heff import _l24, gpu_heff, rel\n"
+        "from paper_2407_07411_amd.heff import Context, SPLIT_BF16X3\n"
+        "prob = _l24(2)\n"
+        "h = gpu_heff(Context(0), prob, prec=SPLIT_BF16X3)\n"
+        "y = h.apply(prob.psi.to('cuda')).cpu().numpy()\n"
+        "torch.cuda.synchronize()\n"
+        "print(json.dumps({'err': rel(y, heff_apply(prob))}), flush=True)\n")
+    env = dict(os.environ, DMRG_HEFF_SPLIT_ACC32="0", DMRG_HEFF_TILE="1288",
+               PYTHONPATH=root + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    print("case split acc64 128x128 child process", flush=True)
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    err = json.loads(out.stdout.strip().splitlines()[-1])["err"]
+    print("split acc64 rel err", err, flush=True)
+    assert 0.0 < err <= SPLIT_TOL
